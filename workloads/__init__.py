@@ -1,0 +1,303 @@
+"""Seeded synthetic inputs shaped like the paper's synthesis workloads.
+
+This module only draws inputs: a 72-depth model atmosphere, a line list, a
+log-uniform wavelength grid and the fitted corrections.  It holds none of the
+synthesis arithmetic (populations, opacity, transfer), so the CPU oracle and
+the GPU path can both consume its output without sharing any method code.
+
+Recipes (all numbers are the workload definitions, not physics of the path):
+
+* Grid (Sec. 2.1, Eqs. 1-2): lambda_i = lambda_first (1 + 1/R)^i with
+  N = floor(ln(lambda_max/lambda_min) / ln(1 + 1/R)) + 1 samples.
+* Atmosphere: column mass m_j = 10^(-3 + 4 j/71) g cm^-2; grey temperature
+  T = Teff [0.75 (tau + 2/3)]^(1/4) with tau = kappa0 m (the grey law of
+  Sec. 4, Eq. 26); n_H = g m / (1.1 k Teff) (hydrostatic equilibrium, Sec. 3
+  Eq. 10, with P_rad = P_0 = 0 and He/H = 0.1); n_e = 1e-4 g m^0.8/(1.1 k Teff);
+  n_pert = n_H; rho = 1.4 m_u n_H.  Power-law continuum kappa0 (lambda /
+  lambda_ref)^alpha with kappa0 = 1 cm^2 g^-1, alpha = -1, lambda_ref the
+  geometric middle of the window.
+* Species: mass ~ U[12, 60] amu, log abundance ~ U[-8, -4] relative to H,
+  ionisation energy ~ U[5, 9] eV, partition functions U_I, U_II ~ U{1..10}
+  (constant with depth).  "Molecular" species carry an infinite ionisation
+  energy (single stage).
+* Lines: log gf ~ U[-4, 0], E ~ U[0, 6] eV, ion stage ~ Bernoulli(1/2),
+  log gamma_rad ~ U[7, 9] s^-1, log gamma_S ~ U[-7, -4] and
+  log gamma_vdW ~ U[-9, -7] cm^3 s^-1 (Table 1 line and broadening symbols).
+
+Seeds: numpy PCG64 with seed 240000 + config index; star b of the batch
+configuration uses 250000 + b.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+K_BOLTZ = 1.380649e-16     # erg/K  (CODATA 2018, exact)
+AMU_G = 1.66053906660e-24  # g
+
+N_DEPTH = 72
+WINDOW_NM = 0.3
+
+
+@dataclasses.dataclass
+class Grid:
+    lam_first_nm: float
+    R: float
+    N: int
+
+
+@dataclasses.dataclass
+class Atmosphere:
+    T: np.ndarray          # [D] K
+    m: np.ndarray          # [D] g cm^-2, strictly increasing inward
+    ne: np.ndarray         # [D] cm^-3
+    npert: np.ndarray      # [D] cm^-3
+    rho: np.ndarray        # [D] g cm^-3
+    n_species: np.ndarray  # [S, D] element (species) totals, cm^-3
+    chi_ion_eV: np.ndarray  # [S] (inf => single stage)
+    U: np.ndarray          # [S, 2, D] partition functions
+    mass_amu: np.ndarray   # [S]
+    kappa0: float = 1.0    # cm^2 g^-1
+    lam_ref_nm: float = 500.0
+    alpha: float = -1.0
+
+    @property
+    def D(self):
+        return int(self.T.shape[0])
+
+    @property
+    def S(self):
+        return int(self.mass_amu.shape[0])
+
+
+@dataclasses.dataclass
+class LineList:
+    lam0_nm: np.ndarray    # [L] float64
+    loggf: np.ndarray      # [L]
+    E_eV: np.ndarray       # [L]
+    species: np.ndarray    # [L] int32
+    ion: np.ndarray        # [L] int32 (0 neutral, 1 singly ionised)
+    log_grad: np.ndarray   # [L] log10 s^-1
+    log_gstark: np.ndarray  # [L] log10 cm^3 s^-1
+    log_gvdw: np.ndarray   # [L] log10 cm^3 s^-1
+
+    @property
+    def L(self):
+        return int(self.lam0_nm.shape[0])
+
+    def take(self, idx):
+        return LineList(*[getattr(self, f.name)[idx] for f in dataclasses.fields(self)])
+
+
+@dataclasses.dataclass
+class Params:
+    dgf: np.ndarray    # [L] dex
+    ddamp: np.ndarray  # [L] dex (scales the total damping width)
+    dA: np.ndarray     # [S] dex
+    xi_kms: float
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    grid: Grid
+    atm: Atmosphere
+    lines: LineList
+    params: Params
+    window_nm: float = WINDOW_NM
+    quadrature: str = "gauss3"
+    extra: dict = dataclasses.field(default_factory=dict)
+
+
+def grid_for(lam_min, lam_max, R):
+    h = math.log1p(1.0 / R)
+    N = int(math.floor(math.log(lam_max / lam_min) / h)) + 1
+    return Grid(float(lam_min), float(R), N)
+
+
+def grid_last(grid):
+    return grid.lam_first_nm * (1.0 + 1.0 / grid.R) ** (grid.N - 1)
+
+
+def make_atmosphere(rng, Teff, logg, S, n_molecular=0, metal_shift=0.0, lam_ref_nm=500.0,
+                    D=N_DEPTH):
+    g = 10.0 ** logg
+    j = np.arange(D, dtype=np.float64)
+    m = 10.0 ** (-3.0 + 4.0 * j / (D - 1))
+    kappa0 = 1.0
+    tau = kappa0 * m
+    T = Teff * (0.75 * (tau + 2.0 / 3.0)) ** 0.25
+    scale = g / (1.1 * K_BOLTZ * Teff)
+    nH = scale * m
+    ne = 1e-4 * scale * m ** 0.8
+    rho = 1.4 * AMU_G * nH
+    mass = rng.uniform(12.0, 60.0, S)
+    logA = rng.uniform(-8.0, -4.0, S) + metal_shift
+    chi = rng.uniform(5.0, 9.0, S)
+    Uc = rng.integers(1, 11, size=(S, 2)).astype(np.float64)
+    if n_molecular:
+        mol = np.arange(S - n_molecular, S)
+        mass[mol] = np.array([26.0, 28.0, 30.0, 32.0][:n_molecular])
+        chi[mol] = np.inf
+    U = np.repeat(Uc[:, :, None], D, axis=2)
+    n_species = (10.0 ** logA)[:, None] * nH[None, :]
+    return Atmosphere(T=T, m=m, ne=ne, npert=nH.copy(), rho=rho, n_species=n_species,
+                      chi_ion_eV=chi, U=U, mass_amu=mass, kappa0=kappa0,
+                      lam_ref_nm=float(lam_ref_nm), alpha=-1.0)
+
+
+def _damping(rng, n):
+    return (rng.uniform(7.0, 9.0, n), rng.uniform(-7.0, -4.0, n), rng.uniform(-9.0, -7.0, n))
+
+
+def atomic_lines(rng, n, lam_lo, lam_hi, n_atomic_species, loggf=None, E_max=6.0, lam0=None):
+    if lam0 is None:
+        lam0 = rng.uniform(lam_lo, lam_hi, n)
+    if loggf is None:
+        loggf = rng.uniform(-4.0, 0.0, n)
+    E = rng.uniform(0.0, E_max, n)
+    sp = rng.integers(0, n_atomic_species, n).astype(np.int32)
+    ion = rng.integers(0, 2, n).astype(np.int32)
+    gr, gs, gw = _damping(rng, n)
+    return LineList(lam0.astype(np.float64), loggf, E, sp, ion, gr, gs, gw)
+
+
+def band_lines(rng, n_bands, per_band, lam_lo, lam_hi, mol_species):
+    """Regularly spaced band-like sequences of 'molecular' lines."""
+    lam, sp = [], []
+    width = lam_hi - lam_lo
+    for _ in range(n_bands):
+        dmax = min(0.05, 0.999 * width / per_band)
+        dlam = rng.uniform(min(0.01, dmax), dmax)
+        head = rng.uniform(lam_lo, lam_hi - dlam * (per_band - 1))
+        lam.append(head + dlam * np.arange(per_band))
+        sp.append(np.full(per_band, rng.choice(mol_species), dtype=np.int32))
+    n = n_bands * per_band
+    lam = np.concatenate(lam) if lam else np.zeros(0)
+    sp = np.concatenate(sp) if sp else np.zeros(0, np.int32)
+    loggf = rng.normal(-2.0, 1.0, n)
+    E = rng.uniform(0.0, 2.0, n)
+    gr, gs, gw = _damping(rng, n)
+    return LineList(lam.astype(np.float64), loggf, E, sp, np.zeros(n, np.int32), gr, gs, gw)
+
+
+def concat_lines(a, b):
+    return LineList(*[np.concatenate([getattr(a, f.name), getattr(b, f.name)])
+                      for f in dataclasses.fields(LineList)])
+
+
+def zero_params(L, S, xi):
+    return Params(np.zeros(L), np.zeros(L), np.zeros(S), float(xi))
+
+
+def config1(seed=240_001):
+    """Plain forward: 500-503 nm, R=300,000, solar, 1,000 lines, 10 species."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = grid_for(500.0, 503.0, 3.0e5)
+    lam_ref = math.sqrt(500.0 * 503.0)
+    atm = make_atmosphere(rng, 5777.0, 4.44, 10, lam_ref_nm=lam_ref)
+    lines = atomic_lines(rng, 1000, 500.0, 503.0, 10)
+    return Workload("500-503nm_R3e5_L1e3_solar", grid, atm, lines, zero_params(1000, 10, 0.7))
+
+
+def _apogee_mixture(rng, L, lam_lo, lam_hi, S_atomic, mol_species):
+    n_band_lines = int(round(0.3 * L / 600.0)) * 600
+    atom = atomic_lines(rng, L - n_band_lines, lam_lo, lam_hi, S_atomic)
+    bands = band_lines(rng, n_band_lines // 600, 600, lam_lo, lam_hi, mol_species)
+    return concat_lines(atom, bands)
+
+
+def config2(seed=240_002, L=200_000):
+    """1500-1700 nm, R=300,000, Arcturus-like giant, 2e5 lines (30% in bands)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = grid_for(1500.0, 1700.0, 3.0e5)
+    lam_ref = math.sqrt(1500.0 * 1700.0)
+    atm = make_atmosphere(rng, 4500.0, 2.5, 20, n_molecular=2, lam_ref_nm=lam_ref)
+    lines = _apogee_mixture(rng, L, 1500.0, 1700.0, 18, [18, 19])
+    return Workload("1500-1700nm_R3e5_L2e5_giant", grid, atm, lines,
+                    zero_params(lines.L, 20, 1.7))
+
+
+def config3(seed=240_003, L=5_000_000):
+    """300-1000 nm, R=300,000, solar, 5e6 lines with density ~ lambda^-2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = 300.0, 1000.0
+    grid = grid_for(lo, hi, 3.0e5)
+    atm = make_atmosphere(rng, 5777.0, 4.44, 40, lam_ref_nm=math.sqrt(lo * hi))
+    u = rng.uniform(0.0, 1.0, L)
+    lam0 = 1.0 / (1.0 / lo - u * (1.0 / lo - 1.0 / hi))
+    loggf = rng.normal(-2.5, 1.2, L)
+    lines = atomic_lines(rng, L, lo, hi, 40, loggf=loggf, lam0=lam0)
+    return Workload("300-1000nm_R3e5_L5e6_solar", grid, atm, lines, zero_params(L, 40, 0.7))
+
+
+def config4(seed=240_004):
+    """Differentiation on the 1500-1700 nm workload: truth perturbation + noise."""
+    wl = config2()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L, S = wl.lines.L, wl.atm.S
+    truth = Params(rng.normal(0.0, 0.05, L), rng.normal(0.0, 0.1, L), rng.normal(0.0, 0.05, S),
+                   wl.params.xi_kms + 0.2)
+    sigma = 0.01
+    noise = rng.normal(0.0, sigma, wl.grid.N)
+    wl.name = "1500-1700nm_R3e5_L2e5_giant_fwdbwd"
+    wl.extra = dict(truth=truth, sigma=sigma, noise=noise)
+    return wl
+
+
+BATCH_N_MAX = None  # set per star from the 1500-1700 nm interval
+
+
+def batch_star(b, seed_base=250_000, S=20):
+    """Star b of the batched configuration (window and line count drawn per star)."""
+    rng = np.random.Generator(np.random.PCG64(seed_base + b))
+    Teff = rng.uniform(3500.0, 7000.0)
+    logg = rng.uniform(1.0, 5.0)
+    feh = rng.uniform(-2.0, 0.5)
+    xi = rng.uniform(0.5, 2.5)
+    R = 3.0e5
+    full = grid_for(1500.0, 1700.0, R)
+    Nb = int(rng.integers(5000, 40001))
+    clamped = Nb > full.N
+    Nb = min(Nb, full.N)
+    i0 = int(rng.integers(0, full.N - Nb + 1))
+    lam_first = 1500.0 * (1.0 + 1.0 / R) ** i0
+    grid = Grid(lam_first, R, Nb)
+    lam_last = grid_last(grid)
+    Lb = int(rng.integers(10_000, 200_001))
+    atm = make_atmosphere(rng, Teff, logg, S, n_molecular=2, metal_shift=feh,
+                          lam_ref_nm=math.sqrt(lam_first * lam_last))
+    lines = _apogee_mixture(rng, Lb, lam_first, lam_last, S - 2, [S - 2, S - 1])
+    wl = Workload("batch_star_%d" % b, grid, atm, lines, zero_params(lines.L, S, xi))
+    wl.extra = dict(Teff=Teff, logg=logg, feh=feh, clamped=clamped)
+    return wl
+
+
+def config5(n_star=256):
+    return [batch_star(b) for b in range(n_star)]
+
+
+def tiny(seed=7, L=12, N=400, D=8, S=3, lam_lo=500.0, R=3.0e5, xi=1.0, window_nm=WINDOW_NM,
+         logg=4.44, Teff=5777.0, n_molecular=0):
+    """Small random case for brute-force and closed-form checks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = Grid(lam_lo, R, N)
+    lam_hi = grid_last(grid)
+    atm = make_atmosphere(rng, Teff, logg, S, n_molecular=n_molecular,
+                          lam_ref_nm=math.sqrt(lam_lo * lam_hi), D=D)
+    lines = atomic_lines(rng, L, lam_lo, lam_hi, S - n_molecular)
+    if n_molecular:
+        lines.species[::3] = S - 1
+        lines.ion[::3] = 0
+    wl = Workload("tiny_%d" % seed, grid, atm, lines, zero_params(L, S, xi), window_nm=window_nm)
+    return wl
+
+
+def random_params(rng, L, S, xi, scale=1.0):
+    return Params(rng.normal(0.0, 0.05 * scale, L), rng.normal(0.0, 0.1 * scale, L),
+                  rng.normal(0.0, 0.05 * scale, S), float(xi))
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
