@@ -1,0 +1,215 @@
+/*
+ * pz.h -- C ABI of the MI355X (gfx950) LTE spectral-synthesis library.
+ *
+ * The library computes, for one fixed 1-D model atmosphere and one line list,
+ * the emergent flux on a log-uniform wavelength grid (Sec. 2.1 of the paper):
+ *
+ *   grid        lambda_i = lambda_first (1 + 1/R)^i, i = 0..N-1        (Eq. 1)
+ *   populations two-stage Saha ionisation, no ionisation lowering      (Sec. 3, Eq. 11)
+ *   line params Doppler width dv^2 = 2kT/m + xi^2, damping ratio
+ *               a = Gamma / (4 pi dnu_D), Gamma = g_rad + g_S n_e + g_vdW n_pert (Eq. 5)
+ *   opacity     kappa_line(i, j) = sum over lines with |lambda_i - lambda_l| <= W of
+ *               (pi e^2 / m_e c) n/(rho U) gf e^{-E/kT} (1 - e^{-h nu_l/kT})
+ *               H(a, v) / (sqrt(pi) dnu_D)                              (Eqs. 3-4)
+ *   continuum   kappa_c = kappa0 (lambda / lambda_ref)^alpha, sigma_c = 0
+ *   transfer    d tau = chi dm (trapezoid, tau_0 = chi_0 m_0), S = B_lambda(T),
+ *               piecewise-linear S, diffusion lower boundary           (Eqs. 6-7)
+ *   flux        F = 2 pi int_0^1 I(0, mu) mu dmu, 3-point Gauss-Legendre in mu,
+ *               per nm, for the total and the continuum-only branch   (Eq. 8)
+ *
+ * plus the vector-Jacobian product for the four corrections of Eq. 30
+ * (Sec. 6): per-line log gf, per-line damping scale, per-species abundance
+ * (at fixed atmosphere) and microturbulence; and a batched launch over many
+ * stars.
+ *
+ * Conventions
+ *   - Units: wavelengths in nm (vacuum), energies in eV, masses in amu,
+ *     densities in cm^-3, column mass in g cm^-2, rho in g cm^-3, damping
+ *     constants as log10 (s^-1 for radiative, cm^3 s^-1 for Stark and van
+ *     der Waals), microturbulence in km/s, flux in erg s^-1 cm^-2 nm^-1.
+ *   - Memory: "host" pointers are read during the call only; "device"
+ *     pointers are caller-owned device allocations that must stay valid until
+ *     the work enqueued on the stream has finished.  The library never frees
+ *     or reallocates caller memory.  A plan owns its own device buffers.
+ *   - Streams: every synth_* call only enqueues work on the given stream and
+ *     returns; no implicit device synchronisation (pz_plan_create is the one
+ *     call that synchronises).
+ *   - Errors: functions return PZ_OK (0) or a negative PZ_E_* code; a
+ *     thread-local message is available from pz_last_error().  All argument
+ *     validation happens before any device work is enqueued.
+ *   - Determinism: no floating-point atomics; results are bitwise
+ *     reproducible run to run, and synth_batch equals the per-star calls.
+ *   - Limits: 2 <= D <= PZ_MAX_DEPTH depths, 1 <= S species, 0 <= L lines.
+ */
+#ifndef PZ_H
+#define PZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PZ_VERSION 1
+#define PZ_MAX_DEPTH 80
+
+#define PZ_OK 0
+#define PZ_E_INVALID_ARG -1   /* null pointer, bad enum, non-positive size      */
+#define PZ_E_SHAPE -2         /* sizes do not match the plan or a limit         */
+#define PZ_E_NOMEM -3         /* device or host allocation failed               */
+#define PZ_E_HIP -4           /* a HIP runtime call failed                      */
+#define PZ_E_NONFINITE -5     /* NaN/Inf in an input that must be finite        */
+#define PZ_E_UNSUPPORTED -6   /* a valid request this build does not implement  */
+
+#define PZ_QUAD_GAUSS3 0      /* 3-point Gauss-Legendre in mu on [0, 1] (Eq. 8) */
+#define PZ_QUAD_E2 1          /* F = 2 pi int S E2 dtau (exponential integral)  */
+
+#define PZ_MODE_FWD 1
+#define PZ_MODE_FWD_BWD 2
+
+typedef struct pz_plan pz_plan;     /* opaque */
+typedef struct pz_batch pz_batch;   /* opaque */
+typedef void* pz_stream;            /* a hipStream_t; NULL = the null stream */
+
+/* Log-uniform synthesis grid (Eq. 1): lambda_i = lambda_first (1 + 1/R)^i. */
+typedef struct {
+    double lam_first_nm;   /* > 0 */
+    double R;              /* R_grid > 0 (model sampling, not resolving power) */
+    int32_t N;             /* number of samples, >= 2 */
+} pz_grid;
+
+/* Line list (Table 1 "Atomic line" and "Broadening" symbols), host arrays of
+ * length L in the caller's order.  Copied into the plan. */
+typedef struct {
+    int32_t L;
+    const double* lam0_nm;      /* line centre, vacuum nm                   */
+    const double* loggf;        /* log10 gf                                  */
+    const double* E_eV;         /* lower-level excitation energy             */
+    const int32_t* species;     /* 0 <= species < S                          */
+    const int32_t* ion;         /* 0 = neutral, 1 = singly ionised            */
+    const double* log_grad;     /* log10 gamma_rad [s^-1]                     */
+    const double* log_gstark;   /* log10 gamma_S per electron [cm^3 s^-1]     */
+    const double* log_gvdw;     /* log10 gamma_vdW per perturber [cm^3 s^-1]  */
+} pz_lines;
+
+/* Plan options. Zero fields take defaults. */
+typedef struct {
+    double window_nm;           /* W: line l reaches pixel i iff |lambda_i - lambda_l| <= W (> 0) */
+    int32_t quadrature;         /* PZ_QUAD_GAUSS3 (default) or PZ_QUAD_E2             */
+    int32_t tile_px;            /* opacity tile width in pixels: 0 = autotuned/default */
+    int32_t lines_per_chunk;    /* lines staged in LDS per step: 0 = default          */
+    int32_t flags;              /* reserved, must be 0                                 */
+} pz_options;
+
+/* One fixed 1-D atmosphere (device arrays, float64, caller-owned).  Depth
+ * index j = 0 is the surface; column mass m is strictly increasing inward. */
+typedef struct {
+    int32_t D;                  /* depths, equals the plan's D                 */
+    int32_t S;                  /* species, equals the plan's S                */
+    const double* T;            /* [D] K                                       */
+    const double* m;            /* [D] g cm^-2                                 */
+    const double* ne;           /* [D] electron density                        */
+    const double* npert;        /* [D] neutral perturber density (n_H)         */
+    const double* rho;          /* [D] mass density                            */
+    const double* n_species;    /* [S*D] total number density of each species  */
+    const double* chi_ion_eV;   /* [S] ionisation energy I -> II; +inf = one stage */
+    const double* U;            /* [S*2*D] partition functions U_{s,r,j}, r = 0, 1 */
+    const double* mass_amu;     /* [S] absorber mass                           */
+    double kappa0;              /* continuum: kappa0 (lambda/lambda_ref)^alpha, cm^2 g^-1 */
+    double lam_ref_nm;
+    double alpha;
+} pz_atmos;
+
+/* Corrections of Eq. 30 (device float32 arrays; NULL means all zero).
+ * gf' = gf 10^dgf, Gamma' = Gamma 10^ddamp, n_s' = n_s 10^dA.  xi_kms is a
+ * device pointer to one float (microturbulence, km/s) and is required. */
+typedef struct {
+    const float* dgf;           /* [L] caller line order, dex */
+    const float* ddamp;         /* [L] caller line order, dex */
+    const float* dA;            /* [S] dex                    */
+    const float* xi_kms;        /* [1]                        */
+} pz_params;
+
+/* Library version (PZ_VERSION). */
+int pz_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* pz_last_error(void);
+
+/* Build a plan: validates the grid and the line list, sorts the lines by
+ * wavelength, computes each line's integer window [i_lo, i_hi] in float64 from
+ * |lambda_i - lambda_l| <= W, bins lines into wavelength tiles and uploads
+ * everything to the current device.  Lines whose window misses the grid are
+ * kept (zero contribution, zero gradient).  Synchronises the device.
+ * n_species = S and n_depth = D fix the atmosphere shape the plan accepts. */
+int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species,
+                   int32_t n_depth, const pz_options* opts, pz_plan** out);
+
+/* Release a plan (NULL is a no-op).  Synchronises the device. */
+void pz_plan_destroy(pz_plan* plan);
+
+/* Query plan sizes: N, L, S, D, tile_px and the number of Voigt evaluations
+ * one forward pass performs (sum over lines of D * window pixels). */
+int pz_plan_info(const pz_plan* plan, int32_t* N, int32_t* L, int32_t* S, int32_t* D,
+                 int32_t* tile_px, int64_t* voigt_evals);
+
+/* Forward synthesis (Secs. 2.1-2.2): writes F[N] and Fc[N] (device float32,
+ * per nm) for the total and the continuum-only branch.  Leaves the line
+ * opacity kappa_line[D][N] and the per-(line, depth) parameters in the plan's
+ * workspace for a following synth_backward with the same inputs. */
+int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
+                  float* F, float* Fc, pz_stream stream);
+
+/* Vector-Jacobian product (Sec. 6, Eq. 30): given dL/dF[N] (device), writes
+ * dL/d dgf[L] and dL/d ddamp[L] (caller line order), dL/d dA[S] and
+ * dL/d xi[1] (per km/s), all device float32.  dL_dFc may be NULL: the
+ * continuum branch depends on none of the corrections, so it is ignored.
+ * Recomputes the forward pass internally (same stream), so it does not depend
+ * on an earlier synth_forward.  Any gradient pointer may be NULL to skip it. */
+int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
+                   const float* dL_dF, const float* dL_dFc,
+                   float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
+                   pz_stream stream);
+
+/* Debug/test entry: line opacity only.  Writes kappa_line as [D][N] float32
+ * (device) for the given atmosphere and corrections. */
+int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
+                    float* kappa_line, pz_stream stream);
+
+/* Debug/test entry: formal solution for a caller-given source function and
+ * optical depth (Eqs. 7-8), both [D][n] float32 device arrays; writes F[n].
+ * Lets closed forms (linear S, Milne-Eddington) pin the transfer kernel. */
+int pz_debug_formal_solve(int32_t D, int32_t n, const float* S, const float* tau,
+                          int32_t quadrature, float* F, pz_stream stream);
+
+/* One star of a batch (all pointers as in synth_forward/synth_backward). */
+typedef struct {
+    const pz_plan* plan;
+    pz_atmos atm;
+    pz_params par;
+    float* F;                    /* [N]  */
+    float* Fc;                   /* [N]  */
+    const float* dL_dF;          /* [N], FWD_BWD only */
+    float* g_loggf;              /* [L], FWD_BWD only (may be NULL) */
+    float* g_damp;               /* [L]  */
+    float* g_abund;              /* [S]  */
+    float* g_xi;                 /* [1]  */
+} pz_star;
+
+/* Prepare a batch of stars with different atmospheres, windows and line
+ * counts: uploads a device table of the stars' pointers and builds the work
+ * queues (per-star plans must stay alive).  Synchronises the device. */
+int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out);
+void pz_batch_destroy(pz_batch* batch);
+
+/* Batched synthesis: all stars' work in persistent work-queue launches
+ * (PZ_MODE_FWD or PZ_MODE_FWD_BWD).  Enqueue-only: no host synchronisation or
+ * allocation, so it may be captured in a hipGraph.  Results are bitwise equal
+ * to per-star synth_forward / synth_backward calls. */
+int synth_batch(const pz_batch* batch, int32_t mode, pz_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PZ_H */

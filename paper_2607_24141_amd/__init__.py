@@ -1,0 +1,303 @@
+"""Python binding of libpz (MI355X / gfx950 LTE spectral synthesis).
+
+Argument marshalling only: every step of the synthesis runs in the HIP
+kernels behind the C ABI declared in include/pz.h.  PyTorch supplies device
+memory and the stream.  Importing this package fails loudly if the library has
+not been built (there is no CPU fallback).
+
+Names follow the C ABI: pz_plan_create, synth_forward, synth_backward,
+synth_batch, pz_line_opacity, pz_debug_formal_solve, ...
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpz.so")
+
+PZ_OK = 0
+PZ_E_INVALID_ARG = -1
+PZ_E_SHAPE = -2
+PZ_E_NOMEM = -3
+PZ_E_HIP = -4
+PZ_E_NONFINITE = -5
+PZ_E_UNSUPPORTED = -6
+PZ_QUAD_GAUSS3 = 0
+PZ_QUAD_E2 = 1
+PZ_MODE_FWD = 1
+PZ_MODE_FWD_BWD = 2
+PZ_MAX_DEPTH = 80
+
+_c_double_p = C.POINTER(C.c_double)
+_c_int_p = C.POINTER(C.c_int32)
+_c_float_p = C.POINTER(C.c_float)
+
+
+class pz_grid(C.Structure):
+    _fields_ = [("lam_first_nm", C.c_double), ("R", C.c_double), ("N", C.c_int32)]
+
+
+class pz_lines(C.Structure):
+    _fields_ = [("L", C.c_int32), ("lam0_nm", _c_double_p), ("loggf", _c_double_p), ("E_eV", _c_double_p),
+                ("species", _c_int_p), ("ion", _c_int_p), ("log_grad", _c_double_p),
+                ("log_gstark", _c_double_p), ("log_gvdw", _c_double_p)]
+
+
+class pz_options(C.Structure):
+    _fields_ = [("window_nm", C.c_double), ("quadrature", C.c_int32), ("tile_px", C.c_int32),
+                ("lines_per_chunk", C.c_int32), ("flags", C.c_int32)]
+
+
+class pz_atmos(C.Structure):
+    _fields_ = [("D", C.c_int32), ("S", C.c_int32), ("T", C.c_void_p), ("m", C.c_void_p), ("ne", C.c_void_p),
+                ("npert", C.c_void_p), ("rho", C.c_void_p), ("n_species", C.c_void_p),
+                ("chi_ion_eV", C.c_void_p), ("U", C.c_void_p), ("mass_amu", C.c_void_p),
+                ("kappa0", C.c_double), ("lam_ref_nm", C.c_double), ("alpha", C.c_double)]
+
+
+class pz_params(C.Structure):
+    _fields_ = [("dgf", C.c_void_p), ("ddamp", C.c_void_p), ("dA", C.c_void_p), ("xi_kms", C.c_void_p)]
+
+
+class pz_star(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("atm", pz_atmos), ("par", pz_params), ("F", C.c_void_p),
+                ("Fc", C.c_void_p), ("dL_dF", C.c_void_p), ("g_loggf", C.c_void_p), ("g_damp", C.c_void_p),
+                ("g_abund", C.c_void_p), ("g_xi", C.c_void_p)]
+
+
+class PzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libpz error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpz.so is not built (%s); run paper_2607_24141_amd/build.py" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    lib.pz_version.restype = C.c_int
+    lib.pz_last_error.restype = C.c_char_p
+    lib.pz_plan_create.argtypes = [C.POINTER(pz_grid), C.POINTER(pz_lines), C.c_int32, C.c_int32,
+                                   C.POINTER(pz_options), C.POINTER(C.c_void_p)]
+    lib.pz_plan_destroy.argtypes = [C.c_void_p]
+    lib.pz_plan_destroy.restype = None
+    lib.pz_plan_info.argtypes = [C.c_void_p] + [_c_int_p] * 5 + [C.POINTER(C.c_int64)]
+    lib.synth_forward.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
+    lib.synth_backward.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.pz_line_opacity.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
+                                    C.c_void_p]
+    lib.pz_debug_formal_solve.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                          C.c_void_p, C.c_void_p]
+    lib.pz_batch_create.argtypes = [C.c_int32, C.POINTER(pz_star), C.POINTER(C.c_void_p)]
+    lib.pz_batch_destroy.argtypes = [C.c_void_p]
+    lib.pz_batch_destroy.restype = None
+    lib.synth_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    for name in ("pz_plan_create", "pz_plan_info", "synth_forward", "synth_backward", "pz_line_opacity",
+                 "pz_debug_formal_solve", "pz_batch_create", "synth_batch"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "pz_plan_info",
+           "synth_forward", "synth_backward", "pz_line_opacity", "pz_debug_formal_solve",
+           "pz_batch_create", "pz_batch_destroy", "synth_batch")
+
+
+def _check(rc):
+    if rc != PZ_OK:
+        raise PzError(rc, lib.pz_last_error().decode())
+    return rc
+
+
+def pz_version():
+    return lib.pz_version()
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------------------- plan
+class Plan:
+    """pz_plan_create / pz_plan_destroy around host line arrays (float64)."""
+
+    def __init__(self, grid, lines, n_species, n_depth, window_nm=0.3, quadrature=PZ_QUAD_GAUSS3,
+                 tile_px=0, lines_per_chunk=0, flags=0):
+        self._keep = {}
+        g = pz_grid(float(grid.lam_first_nm), float(grid.R), int(grid.N))
+
+        def d(name, arr, dt):
+            a = np.ascontiguousarray(arr, dtype=dt)
+            self._keep[name] = a
+            return a.ctypes.data_as(_c_double_p if dt == np.float64 else _c_int_p)
+
+        ln = pz_lines(int(len(lines.lam0_nm)), d("lam0", lines.lam0_nm, np.float64),
+                      d("loggf", lines.loggf, np.float64), d("E", lines.E_eV, np.float64),
+                      d("sp", lines.species, np.int32), d("ion", lines.ion, np.int32),
+                      d("gr", lines.log_grad, np.float64), d("gs", lines.log_gstark, np.float64),
+                      d("gw", lines.log_gvdw, np.float64))
+        opts = pz_options(float(window_nm), int(quadrature), int(tile_px), int(lines_per_chunk), int(flags))
+        h = C.c_void_p()
+        _check(lib.pz_plan_create(C.byref(g), C.byref(ln), int(n_species), int(n_depth), C.byref(opts),
+                                  C.byref(h)))
+        self._keep.clear()
+        self.handle = h
+        self.N, self.L, self.S, self.D, self.tile_px, self.voigt_evals = self.info()
+
+    def info(self):
+        v = [C.c_int32() for _ in range(5)]
+        ev = C.c_int64()
+        _check(lib.pz_plan_info(self.handle, *[C.byref(x) for x in v], C.byref(ev)))
+        return tuple(x.value for x in v) + (ev.value,)
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib.pz_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def plan_for(workload, **kw):
+    return Plan(workload.grid, workload.lines, workload.atm.S, workload.atm.D,
+                window_nm=workload.window_nm,
+                quadrature=PZ_QUAD_GAUSS3 if workload.quadrature == "gauss3" else PZ_QUAD_E2, **kw)
+
+
+# ----------------------------------------------------------------- atmosphere
+class Atmos:
+    """Device copy (float64) of an atmosphere and its pz_atmos descriptor."""
+
+    def __init__(self, atm, device="cuda"):
+        import torch
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
+        self.t = dict(T=f(atm.T), m=f(atm.m), ne=f(atm.ne), npert=f(atm.npert), rho=f(atm.rho),
+                      n_species=f(atm.n_species), chi=f(atm.chi_ion_eV), U=f(atm.U), mass=f(atm.mass_amu))
+        t = self.t
+        self.c = pz_atmos(int(atm.T.shape[0]), int(atm.mass_amu.shape[0]), t["T"].data_ptr(), t["m"].data_ptr(),
+                          t["ne"].data_ptr(), t["npert"].data_ptr(), t["rho"].data_ptr(),
+                          t["n_species"].data_ptr(), t["chi"].data_ptr(), t["U"].data_ptr(),
+                          t["mass"].data_ptr(), float(atm.kappa0), float(atm.lam_ref_nm), float(atm.alpha))
+
+
+class Params:
+    """Device float32 corrections (dgf[L], ddamp[L], dA[S], xi[1]) and pz_params."""
+
+    def __init__(self, dgf, ddamp, dA, xi):
+        self.dgf, self.ddamp, self.dA, self.xi = dgf, ddamp, dA, xi
+        self.c = pz_params(None if dgf is None else dgf.data_ptr(), None if ddamp is None else ddamp.data_ptr(),
+                           None if dA is None else dA.data_ptr(), xi.data_ptr())
+
+    @classmethod
+    def from_host(cls, p, device="cuda"):
+        import torch
+        f = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=device).contiguous()
+        return cls(f(p.dgf), f(p.ddamp), f(p.dA), f([p.xi_kms]))
+
+
+# ------------------------------------------------------------- entry points
+def synth_forward(plan, atm, par, F, Fc, stream=None):
+    _check(lib.synth_forward(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(F), _ptr(Fc), _stream(stream)))
+
+
+def synth_backward(plan, atm, par, dL_dF, g_loggf, g_damp, g_abund, g_xi, dL_dFc=None, stream=None):
+    _check(lib.synth_backward(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(dL_dF), _ptr(dL_dFc),
+                              _ptr(g_loggf), _ptr(g_damp), _ptr(g_abund), _ptr(g_xi), _stream(stream)))
+
+
+def pz_line_opacity(plan, atm, par, kappa, stream=None):
+    _check(lib.pz_line_opacity(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(kappa), _stream(stream)))
+
+
+def pz_debug_formal_solve(S, tau, F, quadrature=PZ_QUAD_GAUSS3, stream=None):
+    D, n = S.shape
+    _check(lib.pz_debug_formal_solve(int(D), int(n), _ptr(S), _ptr(tau), int(quadrature), _ptr(F),
+                                     _stream(stream)))
+
+
+class Batch:
+    """pz_batch_create / synth_batch over a list of pz_star descriptors."""
+
+    def __init__(self, stars):
+        arr = (pz_star * len(stars))(*stars)
+        h = C.c_void_p()
+        _check(lib.pz_batch_create(len(stars), arr, C.byref(h)))
+        self.handle = h
+        self._stars = arr
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib.pz_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def synth_batch(batch, mode, stream=None):
+    _check(lib.synth_batch(batch.handle, int(mode), _stream(stream)))
+
+
+# ---------------------------------------------------------------- autograd
+def _autograd_function():
+    import torch
+
+    class PzSynth(torch.autograd.Function):
+        """F, Fc = PzSynth.apply(plan, atm, dgf, ddamp, dA, xi): gradients for the four corrections."""
+
+        @staticmethod
+        def forward(ctx, plan, atm, dgf, ddamp, dA, xi):
+            dev = xi.device
+            F = torch.empty(plan.N, dtype=torch.float32, device=dev)
+            Fc = torch.empty(plan.N, dtype=torch.float32, device=dev)
+            par = Params(dgf.detach().contiguous(), ddamp.detach().contiguous(), dA.detach().contiguous(),
+                         xi.detach().contiguous())
+            synth_forward(plan, atm, par, F, Fc)
+            ctx.plan, ctx.atm, ctx.par = plan, atm, par
+            ctx.mark_non_differentiable(Fc)
+            return F, Fc
+
+        @staticmethod
+        def backward(ctx, gF, gFc):
+            plan, par = ctx.plan, ctx.par
+            dev = par.xi.device
+            g = [torch.empty(plan.L, dtype=torch.float32, device=dev),
+                 torch.empty(plan.L, dtype=torch.float32, device=dev),
+                 torch.empty(plan.S, dtype=torch.float32, device=dev),
+                 torch.empty(1, dtype=torch.float32, device=dev)]
+            gF = torch.zeros(plan.N, dtype=torch.float32, device=dev) if gF is None else gF.contiguous()
+            synth_backward(plan, ctx.atm, par, gF, *g)
+            return None, None, g[0], g[1], g[2], g[3]
+
+    return PzSynth
+
+
+_PzSynth = None
+
+
+def PzSynth():
+    global _PzSynth
+    if _PzSynth is None:
+        _PzSynth = _autograd_function()
+    return _PzSynth

@@ -1,0 +1,460 @@
+// C ABI of the synthesis library: argument validation, plan construction
+// (sort, integer windows, tile binning, species lists) and the entry points
+// that enqueue the kernels.  No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pz_internal.h"
+
+using namespace pz;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(PZ_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PZ_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+bool finite_all(const double* x, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+// Integer window of one line: all i in [0, N) with |lambda_i - lambda_l| <= W,
+// evaluated in float64 exactly as the definition reads, lambda_i =
+// lambda_first (1 + 1/R)^i.  The pixel set is an interval; the log-space
+// estimate is corrected by direct tests.
+struct Window {
+    int lo, hi;   // lo in [0, N], hi in [-1, N-1]; empty iff lo > hi
+};
+
+Window line_window(double lam_l, double lf, double r1, double h, int N, double W) {
+    auto lam = [&](long i) { return lf * std::pow(r1, (double)i); };
+    auto in = [&](long i) { return std::fabs(lam(i) - lam_l) <= W; };
+    double e = std::log(lam_l / lf) / h;
+    e = std::min(std::max(e, -1.0), (double)N);
+    long c = std::lround(e);
+    c = std::min(std::max(c, 0L), (long)N - 1);
+    long seed = -1;
+    for (long k = std::max(0L, c - 1); k <= std::min((long)N - 1, c + 1); ++k)
+        if (in(k)) {
+            seed = k;
+            break;
+        }
+    if (seed < 0) {
+        // no pixel within W; keep the bounds monotone in lambda for binning
+        if (lam_l < lf) return {0, -1};
+        if (lam_l > lam(N - 1)) return {N, N - 1};
+        return {(int)c + 1, (int)c};
+    }
+    long lo, hi;
+    double el = (lam_l - W > 0.0) ? std::ceil(std::log((lam_l - W) / lf) / h) : 0.0;
+    lo = (long)std::min(std::max(el, 0.0), (double)seed);
+    while (lo > 0 && in(lo - 1)) --lo;
+    while (!in(lo)) ++lo;
+    double eh = std::floor(std::log((lam_l + W) / lf) / h);
+    hi = (long)std::min(std::max(eh, (double)seed), (double)(N - 1));
+    while (hi < N - 1 && in(hi + 1)) ++hi;
+    while (!in(hi)) --hi;
+    return {(int)lo, (int)hi};
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+int pz_version(void) { return PZ_VERSION; }
+
+const char* pz_last_error(void) { return g_err.c_str(); }
+
+int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species, int32_t n_depth,
+                   const pz_options* opts, pz_plan** out) {
+    g_err.clear();
+    if (!out) return fail(PZ_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid || !lines || !opts) return fail(PZ_E_INVALID_ARG, "grid, lines and opts are required");
+    if (!(grid->lam_first_nm > 0.0) || !std::isfinite(grid->lam_first_nm))
+        return fail(PZ_E_INVALID_ARG, "lam_first_nm must be finite and > 0");
+    if (!(grid->R > 0.0) || !std::isfinite(grid->R)) return fail(PZ_E_INVALID_ARG, "R must be finite and > 0");
+    if (grid->N < 2) return fail(PZ_E_SHAPE, "N must be >= 2 (got %d)", grid->N);
+    if (n_species < 1) return fail(PZ_E_SHAPE, "n_species must be >= 1");
+    if (n_depth < 2 || n_depth > PZ_MAX_DEPTH)
+        return fail(PZ_E_SHAPE, "n_depth must be in [2, %d] (got %d)", PZ_MAX_DEPTH, n_depth);
+    if (lines->L < 0) return fail(PZ_E_SHAPE, "L must be >= 0");
+    if (!(opts->window_nm > 0.0) || !std::isfinite(opts->window_nm))
+        return fail(PZ_E_INVALID_ARG, "window_nm must be finite and > 0");
+    if (opts->quadrature != PZ_QUAD_GAUSS3 && opts->quadrature != PZ_QUAD_E2)
+        return fail(PZ_E_INVALID_ARG, "unknown quadrature %d", opts->quadrature);
+    if (opts->quadrature == PZ_QUAD_E2)
+        return fail(PZ_E_UNSUPPORTED, "E2 quadrature is not implemented on the GPU path");
+    int tile_px = opts->tile_px ? opts->tile_px : 64;
+    if (tile_px != 32 && tile_px != 64 && tile_px != 128)
+        return fail(PZ_E_INVALID_ARG, "tile_px must be 0, 32, 64 or 128 (got %d)", opts->tile_px);
+    int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 32;
+    if (chunk < 1 || chunk > 32) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 32]");
+    if (opts->flags != 0) return fail(PZ_E_INVALID_ARG, "flags must be 0");
+    const int L = lines->L, N = grid->N, S = n_species, D = n_depth;
+    if (L > 0) {
+        if (!lines->lam0_nm || !lines->loggf || !lines->E_eV || !lines->species || !lines->ion ||
+            !lines->log_grad || !lines->log_gstark || !lines->log_gvdw)
+            return fail(PZ_E_INVALID_ARG, "a line array is NULL");
+        if (!finite_all(lines->lam0_nm, L) || !finite_all(lines->loggf, L) || !finite_all(lines->E_eV, L) ||
+            !finite_all(lines->log_grad, L) || !finite_all(lines->log_gstark, L) ||
+            !finite_all(lines->log_gvdw, L))
+            return fail(PZ_E_NONFINITE, "non-finite value in the line list");
+        for (int l = 0; l < L; ++l) {
+            if (!(lines->lam0_nm[l] > 0.0)) return fail(PZ_E_INVALID_ARG, "line %d: lam0_nm must be > 0", l);
+            if (lines->species[l] < 0 || lines->species[l] >= S)
+                return fail(PZ_E_INVALID_ARG, "line %d: species %d outside [0, %d)", l, lines->species[l], S);
+            if (lines->ion[l] != 0 && lines->ion[l] != 1)
+                return fail(PZ_E_INVALID_ARG, "line %d: ion stage must be 0 or 1", l);
+        }
+    }
+
+    // ---- host plan
+    const double lf = grid->lam_first_nm, R = grid->R;
+    const double r1 = 1.0 + 1.0 / R;
+    const double h = std::log1p(1.0 / R);
+    std::vector<int> order(L);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return lines->lam0_nm[a] < lines->lam0_nm[b]; });
+    std::vector<double> lam_cm(L), loggf(L), E(L), lgr(L), lgs(L), lgw(L);
+    std::vector<int> spion(L), ic(L), ilo(L), ihi(L), perm(L);
+    std::vector<float> delta(L);
+    int64_t evals = 0;
+    for (int k = 0; k < L; ++k) {
+        const int l = order[k];
+        const double lam = lines->lam0_nm[l];
+        perm[k] = l;
+        lam_cm[k] = lam * 1.0e-7;
+        loggf[k] = lines->loggf[l];
+        E[k] = lines->E_eV[l];
+        lgr[k] = lines->log_grad[l];
+        lgs[k] = lines->log_gstark[l];
+        lgw[k] = lines->log_gvdw[l];
+        spion[k] = lines->species[l] * 2 + lines->ion[l];
+        const Window w = line_window(lam, lf, r1, h, N, opts->window_nm);
+        ilo[k] = w.lo;
+        ihi[k] = w.hi;
+        if (w.hi >= w.lo) evals += (int64_t)(w.hi - w.lo + 1) * D;
+        const double lnr = std::log(lam / lf);
+        double e = std::min(std::max(lnr / h, -1.0e9), 1.0e9);
+        const long a = std::lround(e);
+        ic[k] = (int)a;
+        delta[k] = (float)(lnr - (double)a * h);
+    }
+    // tiles: lines overlapping [t*TP, t*TP+TP-1] form a contiguous range
+    const int n_tiles = (N + tile_px - 1) / tile_px;
+    std::vector<int> pmax_hi(L), smin_lo(L);
+    for (int k = 0; k < L; ++k) pmax_hi[k] = k ? std::max(pmax_hi[k - 1], ihi[k]) : ihi[k];
+    for (int k = L - 1; k >= 0; --k) smin_lo[k] = (k < L - 1) ? std::min(smin_lo[k + 1], ilo[k]) : ilo[k];
+    std::vector<int> tfirst(n_tiles), tlast(n_tiles);
+    for (int t = 0; t < n_tiles; ++t) {
+        const int start = t * tile_px, end = std::min(N - 1, start + tile_px - 1);
+        const int f = (int)(std::lower_bound(pmax_hi.begin(), pmax_hi.end(), start) - pmax_hi.begin());
+        const int g = (int)(std::upper_bound(smin_lo.begin(), smin_lo.end(), end) - smin_lo.begin());
+        tfirst[t] = f;
+        tlast[t] = std::max(f, g);
+    }
+    // species lists over sorted lines (ascending sorted index)
+    std::vector<int> sp_off(S + 1, 0), sp_idx(L);
+    for (int k = 0; k < L; ++k) sp_off[(spion[k] >> 1) + 1]++;
+    for (int s = 0; s < S; ++s) sp_off[s + 1] += sp_off[s];
+    {
+        std::vector<int> fill(sp_off.begin(), sp_off.end() - 1);
+        for (int k = 0; k < L; ++k) sp_idx[fill[spion[k] >> 1]++] = k;
+    }
+
+    // ---- device layout (one allocation)
+    const int Npad = ((N + NPAD - 1) / NPAD) * NPAD;
+    const size_t Ls = (size_t)std::max(L, 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t o_lam = take(Ls * 8), o_gf = take(Ls * 8), o_E = take(Ls * 8), o_lgr = take(Ls * 8),
+                 o_lgs = take(Ls * 8), o_lgw = take(Ls * 8), o_spion = take(Ls * 4), o_ic = take(Ls * 4),
+                 o_delta = take(Ls * 4), o_ilo = take(Ls * 4), o_ihi = take(Ls * 4), o_perm = take(Ls * 4),
+                 o_tf = take((size_t)n_tiles * 4), o_tl = take((size_t)n_tiles * 4),
+                 o_spo = take((size_t)(S + 1) * 4), o_spi = take(Ls * 4), o_pop = take((size_t)S * 2 * D * 8),
+                 o_lp = take(Ls * D * 16), o_kap = take((size_t)D * Npad * 4), o_gk = take((size_t)D * Npad * 4),
+                 o_gl = take(Ls * 3 * 4);
+    pz_plan* p = new (std::nothrow) pz_plan();
+    if (!p) return fail(PZ_E_NOMEM, "host allocation failed");
+    std::memset(p, 0, sizeof *p);
+    PZ_HIP(hipGetDevice(&p->device));
+    char* base = nullptr;
+    hipError_t e = hipMalloc((void**)&base, off);
+    if (e != hipSuccess) {
+        delete p;
+        (void)hipGetLastError();
+        return fail(PZ_E_NOMEM, "hipMalloc of %zu bytes failed: %s", off, hipGetErrorString(e));
+    }
+    p->base = base;
+    p->N = N;
+    p->Npad = Npad;
+    p->L = L;
+    p->S = S;
+    p->D = D;
+    p->tile_px = tile_px;
+    p->chunk = chunk;
+    p->quadrature = opts->quadrature;
+    p->n_tiles = n_tiles;
+    p->lam_first_nm = lf;
+    p->R = R;
+    p->h = h;
+    p->window_nm = opts->window_nm;
+    p->voigt_evals = evals;
+    p->ln.lam_cm = (double*)(base + o_lam);
+    p->ln.loggf = (double*)(base + o_gf);
+    p->ln.E_eV = (double*)(base + o_E);
+    p->ln.lgr = (double*)(base + o_lgr);
+    p->ln.lgs = (double*)(base + o_lgs);
+    p->ln.lgw = (double*)(base + o_lgw);
+    p->ln.spion = (int*)(base + o_spion);
+    p->ln.ic = (int*)(base + o_ic);
+    p->ln.delta = (float*)(base + o_delta);
+    p->ln.ilo = (int*)(base + o_ilo);
+    p->ln.ihi = (int*)(base + o_ihi);
+    p->ln.perm = (int*)(base + o_perm);
+    p->tile_first = (int*)(base + o_tf);
+    p->tile_last = (int*)(base + o_tl);
+    p->sp_off = (int*)(base + o_spo);
+    p->sp_idx = (int*)(base + o_spi);
+    p->pop = (double*)(base + o_pop);
+    p->lp = (float4*)(base + o_lp);
+    p->kappa = (float*)(base + o_kap);
+    p->gk = (float*)(base + o_gk);
+    p->gline = (float*)(base + o_gl);
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    hipError_t ue = hipSuccess;
+    if (L > 0) {
+        const hipError_t r[] = {
+            up(p->ln.lam_cm, lam_cm.data(), (size_t)L * 8), up(p->ln.loggf, loggf.data(), (size_t)L * 8),
+            up(p->ln.E_eV, E.data(), (size_t)L * 8),        up(p->ln.lgr, lgr.data(), (size_t)L * 8),
+            up(p->ln.lgs, lgs.data(), (size_t)L * 8),       up(p->ln.lgw, lgw.data(), (size_t)L * 8),
+            up(p->ln.spion, spion.data(), (size_t)L * 4),   up(p->ln.ic, ic.data(), (size_t)L * 4),
+            up(p->ln.delta, delta.data(), (size_t)L * 4),   up(p->ln.ilo, ilo.data(), (size_t)L * 4),
+            up(p->ln.ihi, ihi.data(), (size_t)L * 4),       up(p->ln.perm, perm.data(), (size_t)L * 4),
+            up(p->sp_idx, sp_idx.data(), (size_t)L * 4)};
+        for (hipError_t x : r)
+            if (x != hipSuccess) ue = x;
+    }
+    if (ue == hipSuccess) ue = up(p->tile_first, tfirst.data(), (size_t)n_tiles * 4);
+    if (ue == hipSuccess) ue = up(p->tile_last, tlast.data(), (size_t)n_tiles * 4);
+    if (ue == hipSuccess) ue = up(p->sp_off, sp_off.data(), (size_t)(S + 1) * 4);
+    // workspaces start defined (pixels beyond N in the padded rows stay zero)
+    if (ue == hipSuccess) ue = hipMemset(p->kappa, 0, (size_t)D * Npad * 4);
+    if (ue == hipSuccess) ue = hipMemset(p->gk, 0, (size_t)D * Npad * 4);
+    if (ue == hipSuccess) ue = hipMemset(p->gline, 0, Ls * 3 * 4);
+    if (ue == hipSuccess) ue = hipDeviceSynchronize();
+    if (ue != hipSuccess) {
+        (void)hipFree(base);
+        delete p;
+        return hip_fail(ue, "plan upload");
+    }
+    *out = p;
+    return PZ_OK;
+}
+
+void pz_plan_destroy(pz_plan* plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->base);
+    delete plan;
+}
+
+int pz_plan_info(const pz_plan* plan, int32_t* N, int32_t* L, int32_t* S, int32_t* D, int32_t* tile_px,
+                 int64_t* voigt_evals) {
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    if (N) *N = plan->N;
+    if (L) *L = plan->L;
+    if (S) *S = plan->S;
+    if (D) *D = plan->D;
+    if (tile_px) *tile_px = plan->tile_px;
+    if (voigt_evals) *voigt_evals = plan->voigt_evals;
+    return PZ_OK;
+}
+
+}  // extern "C"
+
+namespace pz {
+
+int check_atmos(const pz_plan* plan, const pz_atmos* atm) {
+    if (!atm) return fail(PZ_E_INVALID_ARG, "atmosphere is NULL");
+    if (atm->D != plan->D) return fail(PZ_E_SHAPE, "atmosphere has D=%d, plan expects %d", atm->D, plan->D);
+    if (atm->S != plan->S) return fail(PZ_E_SHAPE, "atmosphere has S=%d, plan expects %d", atm->S, plan->S);
+    if (!atm->T || !atm->m || !atm->ne || !atm->npert || !atm->rho || !atm->n_species || !atm->chi_ion_eV ||
+        !atm->U || !atm->mass_amu)
+        return fail(PZ_E_INVALID_ARG, "an atmosphere array is NULL");
+    if (!std::isfinite(atm->kappa0) || !std::isfinite(atm->lam_ref_nm) || !std::isfinite(atm->alpha) ||
+        !(atm->lam_ref_nm > 0.0))
+        return fail(PZ_E_NONFINITE, "continuum parameters must be finite (lam_ref_nm > 0)");
+    return PZ_OK;
+}
+
+int check_params(const pz_params* par) {
+    if (!par) return fail(PZ_E_INVALID_ARG, "params is NULL");
+    if (!par->xi_kms) return fail(PZ_E_INVALID_ARG, "params.xi_kms (device pointer) is required");
+    return PZ_OK;
+}
+
+StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
+    StarDev s;
+    std::memset(&s, 0, sizeof s);
+    s.N = p->N;
+    s.Npad = p->Npad;
+    s.L = p->L;
+    s.S = p->S;
+    s.D = p->D;
+    s.tile_px = p->tile_px;
+    s.n_tiles = p->n_tiles;
+    s.lam_first_nm = p->lam_first_nm;
+    s.h = p->h;
+    s.h_hi = (float)p->h;
+    s.h_lo = (float)(p->h - (double)s.h_hi);
+    s.ln = p->ln;
+    s.tile_first = p->tile_first;
+    s.tile_last = p->tile_last;
+    s.sp_off = p->sp_off;
+    s.sp_idx = p->sp_idx;
+    s.T = atm->T;
+    s.m = atm->m;
+    s.ne = atm->ne;
+    s.npert = atm->npert;
+    s.rho = atm->rho;
+    s.n_species = atm->n_species;
+    s.chi_ion = atm->chi_ion_eV;
+    s.U = atm->U;
+    s.mass = atm->mass_amu;
+    s.kappa0 = atm->kappa0;
+    s.lam_ref_nm = atm->lam_ref_nm;
+    s.alpha = atm->alpha;
+    s.dgf = par->dgf;
+    s.ddamp = par->ddamp;
+    s.dA = par->dA;
+    s.xi = par->xi_kms;
+    s.pop = p->pop;
+    s.lp = p->lp;
+    s.kappa = p->kappa;
+    s.gk = p->gk;
+    s.gline = p->gline;
+    return s;
+}
+
+int enqueue_opacity(const pz_plan* p, const StarDev& s, hipStream_t st) {
+    PZ_HIP(launch_populations(s, st));
+    PZ_HIP(launch_line_params(s, st));
+    PZ_HIP(launch_opacity(s, p->chunk, st));
+    return PZ_OK;
+}
+
+}  // namespace pz
+
+extern "C" {
+
+int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, float* F, float* Fc,
+                  pz_stream stream) {
+    g_err.clear();
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    int rc = check_atmos(plan, atm);
+    if (rc) return rc;
+    if ((rc = check_params(par))) return rc;
+    if (!F || !Fc) return fail(PZ_E_INVALID_ARG, "F and Fc are required");
+    StarDev s = make_star(plan, atm, par);
+    s.F = F;
+    s.Fc = Fc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    PZ_HIP(launch_flux(s, st));
+    return PZ_OK;
+}
+
+int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, const float* dL_dF,
+                   const float* dL_dFc, float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
+                   pz_stream stream) {
+    (void)dL_dFc;
+    g_err.clear();
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    int rc = check_atmos(plan, atm);
+    if (rc) return rc;
+    if ((rc = check_params(par))) return rc;
+    if (!dL_dF) return fail(PZ_E_INVALID_ARG, "dL_dF is required");
+    StarDev s = make_star(plan, atm, par);
+    s.dLdF = dL_dF;
+    s.g_loggf = g_loggf;
+    s.g_damp = g_damp;
+    s.g_abund = g_abund;
+    s.g_xi = g_xi;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    PZ_HIP(launch_reverse_scan(s, st));
+    PZ_HIP(launch_gather(s, st));
+    PZ_HIP(launch_reduce(s, st));
+    return PZ_OK;
+}
+
+int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, float* kappa_line,
+                    pz_stream stream) {
+    g_err.clear();
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    int rc = check_atmos(plan, atm);
+    if (rc) return rc;
+    if ((rc = check_params(par))) return rc;
+    if (!kappa_line) return fail(PZ_E_INVALID_ARG, "kappa_line is required");
+    StarDev s = make_star(plan, atm, par);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    PZ_HIP(hipMemcpy2DAsync(kappa_line, (size_t)plan->N * 4, plan->kappa, (size_t)plan->Npad * 4,
+                            (size_t)plan->N * 4, plan->D, hipMemcpyDeviceToDevice, st));
+    return PZ_OK;
+}
+
+int pz_debug_formal_solve(int32_t D, int32_t n, const float* S, const float* tau, int32_t quadrature, float* F,
+                          pz_stream stream) {
+    g_err.clear();
+    if (D < 2 || D > PZ_MAX_DEPTH) return fail(PZ_E_SHAPE, "D must be in [2, %d]", PZ_MAX_DEPTH);
+    if (n < 0) return fail(PZ_E_SHAPE, "n must be >= 0");
+    if (!S || !tau || !F) return fail(PZ_E_INVALID_ARG, "S, tau and F are required");
+    if (quadrature == PZ_QUAD_E2) return fail(PZ_E_UNSUPPORTED, "E2 quadrature is not implemented on the GPU path");
+    if (quadrature != PZ_QUAD_GAUSS3) return fail(PZ_E_INVALID_ARG, "unknown quadrature %d", quadrature);
+    if (n == 0) return PZ_OK;
+    PZ_HIP(launch_debug_formal(D, n, S, tau, F, (hipStream_t)stream));
+    return PZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal structures shared by the library's host code and kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pz.h"
+
+namespace pz {
+
+// CODATA 2018, CGS
+static constexpr double C_LIGHT = 2.99792458e10;
+static constexpr double H_PLANCK = 6.62607015e-27;
+static constexpr double K_BOLTZ = 1.380649e-16;
+static constexpr double E_CHARGE = 4.803204712570263e-10;
+static constexpr double M_ELECTRON = 9.1093837015e-28;
+static constexpr double AMU_G = 1.66053906660e-24;
+static constexpr double EV_ERG = 1.602176634e-12;
+static constexpr double PI = 3.14159265358979323846;
+static constexpr double LN10 = 2.30258509299404568402;
+
+static constexpr int MAXD = PZ_MAX_DEPTH;
+static constexpr int NPAD = 256;          // row padding of [D][Npad] workspaces
+
+// Per-line data of a plan, in wavelength-sorted order (device SoA).
+struct LineArrays {
+    double* lam_cm;      // line centre, cm
+    double* loggf;
+    double* E_eV;
+    double* lgr;         // log10 gamma_rad
+    double* lgs;         // log10 gamma_S
+    double* lgw;         // log10 gamma_vdW
+    int* spion;          // species * 2 + ion
+    int* ic;             // anchor pixel: nearest grid index to the line centre
+    float* delta;        // ln(lambda_l / lambda_ic), |delta| <= h/2
+    int* ilo;            // window [ilo, ihi] (empty: ilo > ihi)
+    int* ihi;
+    int* perm;           // sorted index -> caller index
+};
+
+// Everything a kernel needs about one star (plan + atmosphere + corrections +
+// outputs + workspaces).  Passed by value or stored in the batch table.
+struct StarDev {
+    // grid
+    int N, Npad, L, S, D, tile_px, n_tiles;
+    double lam_first_nm, h;      // h = ln(1 + 1/R)
+    float h_hi, h_lo;            // h split for float32 offsets
+    LineArrays ln;
+    const int* tile_first;       // [n_tiles]
+    const int* tile_last;        // [n_tiles]
+    const int* sp_off;           // [S+1] species CSR over sorted lines
+    const int* sp_idx;           // [L]
+    // atmosphere (caller device memory, float64)
+    const double* T;
+    const double* m;
+    const double* ne;
+    const double* npert;
+    const double* rho;
+    const double* n_species;
+    const double* chi_ion;
+    const double* U;
+    const double* mass;
+    double kappa0, lam_ref_nm, alpha;
+    // corrections (caller device memory; may be null except xi)
+    const float* dgf;
+    const float* ddamp;
+    const float* dA;
+    const float* xi;
+    // outputs
+    float* F;
+    float* Fc;
+    const float* dLdF;
+    float* g_loggf;
+    float* g_damp;
+    float* g_abund;
+    float* g_xi;
+    // plan workspaces
+    double* pop;                 // [S][2][D] n/(rho U) including 10^dA
+    float4* lp;                  // [L][D] (s = c/dv, a, K, dlnDnu/dxi per km/s)
+    float* kappa;                // [D][Npad]
+    float* gk;                   // [D][Npad] dL/dkappa_line
+    float* gline;                // [3][L] per-line sums (sorted order)
+};
+
+// Kernel launchers (pz_kernels.hip).  Each enqueues on the stream and returns
+// the hipError_t of the launch.
+hipError_t launch_populations(const StarDev& s, hipStream_t st);
+hipError_t launch_line_params(const StarDev& s, hipStream_t st);
+hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st);
+hipError_t launch_flux(const StarDev& s, hipStream_t st);
+hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st);
+hipError_t launch_gather(const StarDev& s, hipStream_t st);
+hipError_t launch_reduce(const StarDev& s, hipStream_t st);
+hipError_t launch_debug_formal(int D, int n, const float* S, const float* tau, float* F,
+                               hipStream_t st);
+
+}  // namespace pz
+
+struct pz_plan {
+    int device;
+    int N, Npad, L, S, D, tile_px, chunk, quadrature;
+    int n_tiles;
+    double lam_first_nm, R, h, window_nm;
+    int64_t voigt_evals;
+    pz::LineArrays ln;
+    int* tile_first;
+    int* tile_last;
+    int* sp_off;
+    int* sp_idx;
+    double* pop;
+    float4* lp;
+    float* kappa;
+    float* gk;
+    float* gline;
+    void* base;          // single device allocation holding everything above
+};

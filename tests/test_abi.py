@@ -1,0 +1,108 @@
+"""The C-ABI library loads and exports every function include/pz.h declares;
+argument validation runs on the host before any device work (no GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pz.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+@pytest.fixture(scope="module")
+def pz():
+    import paper_2607_24141_amd as pz
+    return pz
+
+
+def test_exports_every_declared_symbol(pz):
+    declared = _declared()
+    assert {"synth_forward", "synth_backward", "synth_batch", "pz_plan_create"} <= set(declared)
+    for name in declared:
+        assert hasattr(pz.lib, name), name
+    assert set(declared) == set(pz.EXPORTS)
+
+
+def test_version(pz):
+    assert pz.pz_version() == 1
+
+
+def _lines(pz, L=3, **over):
+    import numpy as np
+    d = dict(lam0=np.array([500.1, 500.2, 500.3])[:L], loggf=np.zeros(L), E=np.ones(L),
+             sp=np.zeros(L, np.int32), ion=np.zeros(L, np.int32), gr=np.full(L, 8.0), gs=np.full(L, -5.0),
+             gw=np.full(L, -8.0))
+    d.update(over)
+    keep = [np.ascontiguousarray(d[k], np.float64 if k not in ("sp", "ion") else np.int32) for k in
+            ("lam0", "loggf", "E", "sp", "ion", "gr", "gs", "gw")]
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    ln = pz.pz_lines(L, dp(keep[0]), dp(keep[1]), dp(keep[2]), ip(keep[3]), ip(keep[4]), dp(keep[5]),
+                     dp(keep[6]), dp(keep[7]))
+    return ln, keep
+
+
+def _create(pz, grid=None, lines=None, S=2, D=8, opts=None):
+    g = grid or pz.pz_grid(500.0, 3e5, 100)
+    ln, keep = lines if lines is not None else _lines(pz)
+    o = opts or pz.pz_options(0.3, 0, 0, 0, 0)
+    h = C.c_void_p()
+    rc = pz.lib.pz_plan_create(C.byref(g), C.byref(ln), S, D, C.byref(o), C.byref(h))
+    return rc, pz.lib.pz_last_error().decode()
+
+
+@pytest.mark.parametrize("case,code", [
+    ("N", -2), ("R", -1), ("lam", -1), ("D", -2), ("Dbig", -2), ("S", -2), ("W", -1), ("quad", -1),
+    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5), ("e2", -6)])
+def test_plan_validation(pz, case, code):
+    import numpy as np
+    kw = {}
+    if case == "N":
+        kw["grid"] = pz.pz_grid(500.0, 3e5, 1)
+    elif case == "R":
+        kw["grid"] = pz.pz_grid(500.0, -1.0, 100)
+    elif case == "lam":
+        kw["grid"] = pz.pz_grid(float("nan"), 3e5, 100)
+    elif case == "D":
+        kw["D"] = 1
+    elif case == "Dbig":
+        kw["D"] = pz.PZ_MAX_DEPTH + 1
+    elif case == "S":
+        kw["S"] = 0
+    elif case == "W":
+        kw["opts"] = pz.pz_options(0.0, 0, 0, 0, 0)
+    elif case == "quad":
+        kw["opts"] = pz.pz_options(0.3, 7, 0, 0, 0)
+    elif case == "tile":
+        kw["opts"] = pz.pz_options(0.3, 0, 48, 0, 0)
+    elif case == "flags":
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 1)
+    elif case == "species":
+        kw["lines"] = _lines(pz, sp=np.array([0, 5, 0], np.int32))
+    elif case == "ion":
+        kw["lines"] = _lines(pz, ion=np.array([0, 2, 0], np.int32))
+    elif case == "nan":
+        kw["lines"] = _lines(pz, loggf=np.array([0.0, np.nan, 0.0]))
+    elif case == "e2":
+        kw["opts"] = pz.pz_options(0.3, 1, 0, 0, 0)
+    rc, msg = _create(pz, **kw)
+    assert rc == code, (rc, msg)
+    assert msg
+
+
+def test_entry_points_reject_null_before_device_work(pz):
+    assert pz.lib.synth_forward(None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.synth_backward(None, None, None, None, None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_line_opacity(None, None, None, None, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_debug_formal_solve(1, 4, None, None, 0, None, None) == pz.PZ_E_SHAPE
+    assert pz.lib.pz_debug_formal_solve(8, 4, None, None, 0, None, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.synth_batch(None, 1, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_plan_info(None, None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG

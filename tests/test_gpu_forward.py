@@ -1,0 +1,164 @@
+"""GPU forward parity against the FP64 oracle, through the C ABI.
+
+Tolerances: the synthesis must match the oracle to 1e-4 relative flux in
+float32 (F, F_c and F/F_c).  The opacity diagnostic uses 2e-5 relative to
+kappa_line + 1e-6 kappa_c (float32 rounding of the per-(line, depth)
+parameters, ~1e-6 Voigt error, float32 accumulation).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import synth as O
+
+pytestmark = pytest.mark.gpu
+FLUX_RTOL = 1e-4
+
+
+def _run_forward(pz, wl, plan=None, params=None):
+    plan = plan or pz.plan_for(wl)
+    atm = pz.Atmos(wl.atm)
+    par = pz.Params.from_host(params or wl.params)
+    F = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+    Fc = torch.empty_like(F)
+    print("synth_forward", wl.name, "N", plan.N, "L", plan.L, flush=True)
+    pz.synth_forward(plan, atm, par, F, Fc)
+    torch.cuda.synchronize()
+    return F.cpu().numpy().astype(np.float64), Fc.cpu().numpy().astype(np.float64)
+
+
+def _flux_close(F, Fc, Fo, Fco):
+    for got, ref, name in ((F, Fo, "F"), (Fc, Fco, "Fc"), (F / Fc, Fo / Fco, "f")):
+        rel = np.abs(got - ref) / np.abs(ref)
+        assert rel.max() <= FLUX_RTOL, (name, rel.max(), int(np.argmax(rel)))
+    return float(np.max(np.abs(F / Fc - Fo / Fco) / (Fo / Fco)))
+
+
+@pytest.mark.parametrize("seed,L,N,D,tile", [(1, 12, 400, 8, 0), (2, 40, 777, 10, 32), (3, 25, 1000, 6, 128),
+                                             (4, 60, 513, 72, 64)])
+def test_line_opacity_tiny(gpu_lib, seed, L, N, D, tile):
+    pz = gpu_lib
+    wl = W.tiny(seed=seed, L=L, N=N, D=D, S=4, n_molecular=1)
+    wl.params = W.random_params(np.random.default_rng(seed), L, 4, 1.2)
+    plan = pz.plan_for(wl, tile_px=tile)
+    atm = pz.Atmos(wl.atm)
+    par = pz.Params.from_host(wl.params)
+    kap = torch.empty((D, N), dtype=torch.float32, device="cuda")
+    print("pz_line_opacity", seed, L, N, D, tile, flush=True)
+    pz.pz_line_opacity(plan, atm, par, kap)
+    torch.cuda.synchronize()
+    got = kap.cpu().numpy().astype(np.float64)
+    ref = O.line_opacity(wl, wl.params)
+    kc = O.continuum_opacity(wl)[None, :]
+    err = np.abs(got - ref) / (ref + 1e-6 * kc)
+    assert err.max() <= 2e-5, (err.max(), np.unravel_index(np.argmax(err), err.shape))
+
+
+def test_flux_500_503nm_full(gpu_lib):
+    """1,795-pixel, 1,000-line solar case: every pixel vs the oracle."""
+    wl = W.config1()
+    F, Fc = _run_forward(gpu_lib, wl)
+    Fo, Fco = O.synthesize(wl)
+    print("max rel f err", _flux_close(F, Fc, Fo, Fco))
+
+
+def test_empty_catalog_total_equals_continuum(gpu_lib):
+    wl = W.tiny(L=0, N=300, D=8)
+    F, Fc = _run_forward(gpu_lib, wl)
+    np.testing.assert_array_equal(F, Fc)
+    Fo, Fco = O.synthesize(wl)
+    np.testing.assert_allclose(Fc, Fco, rtol=FLUX_RTOL)
+
+
+def test_lines_outside_grid_and_ragged_tail(gpu_lib):
+    """Lines beyond both ends (windows partly or wholly off the grid), N not a tile multiple."""
+    wl = W.tiny(seed=17, L=30, N=301, D=8)
+    lam = O.wavelengths_nm(wl.grid)
+    wl.lines.lam0_nm[:6] = lam[0] - np.array([0.05, 0.2, 0.29, 0.31, 1.0, 50.0])
+    wl.lines.lam0_nm[6:12] = lam[-1] + np.array([0.05, 0.2, 0.29, 0.31, 1.0, 50.0])
+    F, Fc = _run_forward(gpu_lib, wl)
+    Fo, Fco = O.synthesize(wl)
+    _flux_close(F, Fc, Fo, Fco)
+
+
+def test_deterministic_bitwise(gpu_lib):
+    wl = W.tiny(seed=5, L=200, N=2000, D=72)
+    plan = gpu_lib.plan_for(wl)
+    a = _run_forward(gpu_lib, wl, plan)
+    b = _run_forward(gpu_lib, wl, plan)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("tile", [32, 64, 128])
+def test_tile_width_invariance(gpu_lib, tile):
+    """Any tile width gives the same flux to float32 rounding."""
+    wl = W.tiny(seed=6, L=150, N=1500, D=72)
+    F, Fc = _run_forward(gpu_lib, wl, gpu_lib.plan_for(wl, tile_px=tile))
+    Fo, Fco = O.synthesize(wl)
+    _flux_close(F, Fc, Fo, Fco)
+
+
+# -------------------------------------------------------- formal solution
+def _formal(pz, S, tau):
+    St = torch.as_tensor(S.astype(np.float32), device="cuda").contiguous()
+    Tt = torch.as_tensor(tau.astype(np.float32), device="cuda").contiguous()
+    F = torch.empty(S.shape[1], dtype=torch.float32, device="cuda")
+    pz.pz_debug_formal_solve(St, Tt, F)
+    torch.cuda.synchronize()
+    return F.cpu().numpy().astype(np.float64)
+
+
+def test_formal_solution_linear_source(gpu_lib):
+    """S = a + b tau => F = pi (a + 2b/3) exactly (Eqs. 7-8)."""
+    tau = np.geomspace(1e-4, 50.0, 72)[:, None] * np.array([1.0, 0.3, 3.0, 10.0])[None, :]
+    a, b = 2.0, 3.0
+    F = _formal(gpu_lib, a + b * tau, tau)
+    np.testing.assert_allclose(F, math.pi * (a + 2 * b / 3), rtol=2e-6)
+
+
+def test_formal_solution_milne_eddington(gpu_lib):
+    tc = np.geomspace(1e-4, 60.0, 72)[:, None] * np.ones((1, 4))
+    eta = np.array([0.0, 0.3, 5.0, 300.0])[None, :]
+    a, b = 1.0, 2.5
+    S = a + b * tc
+    ratio = _formal(gpu_lib, S, tc * (1 + eta)) / _formal(gpu_lib, S, tc)
+    expect = (a + 2 * b / (3 * (1 + eta[0]))) / (a + 2 * b / 3)
+    np.testing.assert_allclose(ratio, expect, rtol=2e-6)
+
+
+def test_formal_solution_curved_source(gpu_lib):
+    """A curved source against the oracle's formal solution (same quadrature)."""
+    tau = np.geomspace(1e-3, 30.0, 72)[:, None] * np.array([1.0, 2.0])[None, :]
+    S = np.exp(-1.0 / (0.3 + tau)) + 0.2 * np.sqrt(tau)
+    np.testing.assert_allclose(_formal(gpu_lib, S, tau), O.flux_gauss3(S, tau), rtol=1e-5)
+
+
+# ------------------------------------------------- full-size, sampled pixels
+def _sample_pixels(N, rng, n=96, tile=64):
+    fixed = [0, 1, 2, tile - 1, tile, tile + 1, N // 2, N - 3, N - 2, N - 1]
+    return np.unique(np.concatenate([fixed, rng.integers(0, N, n)]))
+
+
+def test_flux_1500_1700nm_sampled(gpu_lib):
+    """37,550 pixels, 2e5 lines (30% in bands): sampled pixels vs the oracle."""
+    wl = W.config2()
+    F, Fc = _run_forward(gpu_lib, wl)
+    pix = _sample_pixels(wl.grid.N, np.random.default_rng(0))
+    Fo, Fco = O.synthesize(wl, pix=pix)
+    print("max rel f err", _flux_close(F[pix], Fc[pix], Fo, Fco))
+    assert np.all(np.isfinite(F)) and np.all(F > 0) and np.all(F <= Fc * (1 + 1e-6))
+
+
+def test_flux_300_1000nm_sampled(gpu_lib):
+    """361,193 pixels, 5e6 lines with density ~ lambda^-2: sampled pixels vs the oracle."""
+    wl = W.config3()
+    F, Fc = _run_forward(gpu_lib, wl)
+    rng = np.random.default_rng(1)
+    pix = np.unique(np.concatenate([_sample_pixels(wl.grid.N, rng, n=24), rng.integers(0, 3000, 8)]))
+    Fo, Fco = O.synthesize(wl, pix=pix)
+    print("max rel f err", _flux_close(F[pix], Fc[pix], Fo, Fco))
+    assert np.all(np.isfinite(F)) and np.all(F > 0)
