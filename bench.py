@@ -1,0 +1,239 @@
+"""Benchmark of the MI355X synthesis path (one JSON line on stdout).
+
+value: forward spectra/s on the 1500-1700 nm, R = 300,000 workload (37,550
+pixels x 72 depths, 2e5 lines, 30 % in molecular-band-like sequences), inputs
+resident in HBM, K timed steps between device synchronisations.  A step is
+one whole forward synthesis (populations, line parameters, windowed Voigt
+opacity, depth scan and Gauss-3 flux for both branches).  Extra fields: the
+forward+backward step (chi^2 loss seed and the adjoint for all 4e5 + 20 + 1
+corrections) and the batched launch over 256 stars, the roofline of the
+dominant kernel (opacity) and the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes fwd,fwdbwd,batch] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spectra/s, Voigt evals/s: fwd, fwd+bwd, batched vs plain fwd at 1e-4 rel"
+# Algorithmic float32 operations of one Voigt evaluation (one line, one depth,
+# one in-window pixel) in the wing formula, FMA = 2: detuning scale and u = v^2
+# (2), a^2, u - a^2, 4 u a^2, u + a^2 (5), three node pairs x (sub, FMA, add, mul,
+# rcp, FMA = 8), a * sum (1), kappa += K H (2).
+FLOPS_PER_EVAL = 34
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+KERNEL_SOURCES = ("paper_2607_24141_amd/csrc/pz_kernels.hip", "paper_2607_24141_amd/csrc/pz_voigt.h",
+                  "paper_2607_24141_amd/csrc/voigt_consts.h")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kind="opacity"):
+    """HBM bytes per launch from the committed counter summary, if it was taken on these sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kind)
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(wl, target_s=12.0):
+    """The FP64 oracle on a bounded pixel sample of the same workload, scaled to spectra/s."""
+    import numpy as np
+    from oracle import synth as O
+    rng = np.random.default_rng(0)
+    done, t = 0, 0.0
+    while t < target_s and done < wl.grid.N:
+        pix = np.sort(rng.choice(wl.grid.N, 32, replace=False))
+        t0 = time.perf_counter()
+        O.synthesize(wl, pix=pix)
+        t += time.perf_counter() - t0
+        done += pix.size
+    per_spectrum = t / done * wl.grid.N
+    return {"value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": 1, "kind": "oracle",
+            "sample": "%d random pixels of the %d-pixel spectrum (all lines within W of each), "
+                      "%.1f s of single-threaded numpy/scipy FP64, scaled to the full spectrum"
+                      % (done, wl.grid.N, t),
+            "voigt_evals_per_s": None}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--modes", default="fwd,fwdbwd,batch")
+    ap.add_argument("--batch-stars", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    modes = set(args.modes.split(","))
+
+    import numpy as np
+    import torch
+
+    import paper_2607_24141_amd as pz
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    log("generating 1500-1700 nm workload")
+    wl = W.config4()
+    plan = pz.plan_for(wl)
+    atm = pz.Atmos(wl.atm)
+    par = pz.Params.from_host(wl.params)
+    N, L, S = plan.N, plan.L, plan.S
+    F = torch.empty(N, dtype=torch.float32, device=dev)
+    Fc = torch.empty_like(F)
+
+    # ---- forward (the headline)
+    log("forward: N=%d L=%d evals=%.3e" % (N, L, plan.voigt_evals))
+    fwd = lambda: pz.synth_forward(plan, atm, par, F, Fc)
+    fwd()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    ms_fwd, wall_fwd = timed(fwd, args.steps, args.warmup, torch)
+    prof = plan.profile_read()
+    plan.profile(False)
+    op_ms, op_n = prof["opacity"]
+    op_avg_ms = op_ms / max(op_n, 1)
+    achieved_tflops = plan.voigt_evals * FLOPS_PER_EVAL / (op_avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_fwd,
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_fwd,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name.replace("_fwdbwd", ""), "lambda_nm": [1500, 1700], "R": 3.0e5,
+                   "N": N, "D": plan.D, "L": L, "S": S, "window_nm": wl.window_nm, "quadrature": "gauss3",
+                   "mode": "fwd", "tile_px": plan.tile_px},
+        "voigt_evals_per_s": plan.voigt_evals / (ms_fwd * 1e-3),
+        "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
+        "roofline": {"bound": "alu", "kernel": "k_opacity", "achieved": achieved_tflops,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+                     "traffic": traffic_from_profiles("opacity"), "kernel_avg_ms": op_avg_ms,
+                     "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": plan.voigt_evals},
+        "wall_s_timed": wall_fwd,
+    }
+
+    # ---- forward + backward with the chi^2 loss (S/N = 100)
+    if "fwdbwd" in modes:
+        sigma = wl.extra["sigma"]
+        y = torch.as_tensor(np.ones(N, np.float32), device=dev)
+        # target: synthesis at the perturbed (truth) corrections plus noise
+        tpar = pz.Params.from_host(wl.extra["truth"])
+        Ft, Fct = torch.empty_like(F), torch.empty_like(F)
+        pz.synth_forward(plan, atm, tpar, Ft, Fct)
+        y = (Ft / Fct + torch.as_tensor(wl.extra["noise"].astype(np.float32), device=dev)).contiguous()
+        gF = torch.empty_like(F)
+        gFc = torch.empty_like(F)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        g = [torch.empty(L, device=dev), torch.empty(L, device=dev), torch.empty(S, device=dev),
+             torch.empty(1, device=dev)]
+
+        def fb():
+            pz.synth_forward(plan, atm, par, F, Fc)
+            pz.pz_chi2_seed(F, Fc, y, sigma, gF, gFc, loss)
+            pz.synth_backward(plan, atm, par, gF, *g)
+
+        log("forward+backward")
+        plan.profile(True)
+        ms_fb, _ = timed(fb, args.steps, args.warmup, torch)
+        prof_fb = plan.profile_read()
+        plan.profile(False)
+        out["fwd_bwd"] = {"spectra_per_s": 1000.0 / ms_fb, "ms_per_step": ms_fb, "ratio_to_fwd": ms_fb / ms_fwd,
+                          "voigt_evals_per_s": 2 * plan.voigt_evals / (ms_fb * 1e-3),
+                          "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof_fb.items() if v[1]}}
+
+    # ---- batched forward + backward over many stars
+    if "batch" in modes:
+        nb = args.batch_stars
+        log("generating %d-star batch" % nb)
+        from concurrent.futures import ThreadPoolExecutor
+        stars_wl = [W.batch_star(b) for b in range(nb)]
+        with ThreadPoolExecutor(16) as ex:
+            plans = list(ex.map(lambda w: pz.plan_for(w), stars_wl))
+        keep = []
+        descr = []
+        total_evals = 0
+        for w, p in zip(stars_wl, plans):
+            a = pz.Atmos(w.atm)
+            q = pz.Params.from_host(w.params)
+            bufs = dict(F=torch.empty(p.N, device=dev), Fc=torch.empty(p.N, device=dev),
+                        seed=torch.randn(p.N, device=dev) * 1e-6,
+                        gl=torch.empty(p.L, device=dev), gd=torch.empty(p.L, device=dev),
+                        ga=torch.empty(p.S, device=dev), gx=torch.empty(1, device=dev))
+            keep.append((a, q, bufs))
+            descr.append(pz.pz_star(p.handle.value, a.c, q.c, bufs["F"].data_ptr(), bufs["Fc"].data_ptr(),
+                                    bufs["seed"].data_ptr(), bufs["gl"].data_ptr(), bufs["gd"].data_ptr(),
+                                    bufs["ga"].data_ptr(), bufs["gx"].data_ptr()))
+            total_evals += p.voigt_evals
+        batch = pz.Batch(descr)
+        log("batch: %d stars, %.3e evals per forward" % (nb, total_evals))
+        bsteps = max(2, args.steps // 4)
+        ms_bf, _ = timed(lambda: pz.synth_batch(batch, pz.PZ_MODE_FWD), bsteps, 1, torch)
+        ms_bb, _ = timed(lambda: pz.synth_batch(batch, pz.PZ_MODE_FWD_BWD), bsteps, 1, torch)
+        out["batched"] = {"stars": nb, "fwd_spectra_per_s": nb * 1000.0 / ms_bf, "fwd_ms": ms_bf,
+                          "fwd_bwd_spectra_per_s": nb * 1000.0 / ms_bb, "fwd_bwd_ms": ms_bb,
+                          "fwd_voigt_evals_per_s": total_evals / (ms_bf * 1e-3),
+                          "fwd_bwd_over_fwd": ms_bb / ms_bf}
+        batch.destroy()
+        for p in plans:
+            p.destroy()
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cb = cpu_baseline(W.config2())
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

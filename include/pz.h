@@ -171,6 +171,13 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
                    float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
                    pz_stream stream);
 
+/* Loss seed of a chi^2 fit to a normalised spectrum: with f = F / Fc (Eq. 9,
+ * identity instrument operator) and L = sum_i ((f_i - y_i) / sigma)^2 (the
+ * chi^2 objective of Sec. 5), writes dL/dF[N], dL/dFc[N] and L[1] (device
+ * float32; dL_dFc and loss may be NULL).  The sum runs in a fixed order. */
+int pz_chi2_seed(int32_t N, const float* F, const float* Fc, const float* y, float sigma,
+                 float* dL_dF, float* dL_dFc, float* loss, pz_stream stream);
+
 /* Debug/test entry: line opacity only.  Writes kappa_line as [D][N] float32
  * (device) for the given atmosphere and corrections. */
 int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
@@ -181,6 +188,25 @@ int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* p
  * Lets closed forms (linear S, Milne-Eddington) pin the transfer kernel. */
 int pz_debug_formal_solve(int32_t D, int32_t n, const float* S, const float* tau,
                           int32_t quadrature, float* F, pz_stream stream);
+
+/* Stage profiling.  While enabled, every kernel launch of this plan is
+ * bracketed by hipEvents recorded on the launch stream (no host
+ * synchronisation is added); pz_plan_profile_read synchronises on the recorded
+ * events and returns, per stage, the summed duration in ms and the launch
+ * count since profiling was enabled.  At most PZ_PROFILE_SLOTS launches per
+ * stage are recorded; later ones are not timed (counted in *count only up to
+ * the limit).  Stages: PZ_STAGE_*. */
+#define PZ_STAGE_POPULATIONS 0
+#define PZ_STAGE_LINE_PARAMS 1
+#define PZ_STAGE_OPACITY 2
+#define PZ_STAGE_FLUX 3
+#define PZ_STAGE_REVERSE_SCAN 4
+#define PZ_STAGE_GATHER 5
+#define PZ_STAGE_REDUCE 6
+#define PZ_N_STAGES 7
+#define PZ_PROFILE_SLOTS 512
+int pz_plan_profile(pz_plan* plan, int32_t enable);
+int pz_plan_profile_read(pz_plan* plan, double* total_ms /*[PZ_N_STAGES]*/, int32_t* count /*[PZ_N_STAGES]*/);
 
 /* One star of a batch (all pointers as in synth_forward/synth_backward). */
 typedef struct {

@@ -30,6 +30,8 @@ PZ_QUAD_E2 = 1
 PZ_MODE_FWD = 1
 PZ_MODE_FWD_BWD = 2
 PZ_MAX_DEPTH = 80
+PZ_N_STAGES = 7
+STAGES = ("populations", "line_params", "opacity", "flux", "reverse_scan", "gather", "reduce")
 
 _c_double_p = C.POINTER(C.c_double)
 _c_int_p = C.POINTER(C.c_int32)
@@ -93,11 +95,15 @@ def _load():
                                     C.c_void_p]
     lib.pz_debug_formal_solve.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_void_p, C.c_void_p]
+    lib.pz_chi2_seed.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.pz_plan_profile.argtypes = [C.c_void_p, C.c_int32]
+    lib.pz_plan_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), _c_int_p]
     lib.pz_batch_create.argtypes = [C.c_int32, C.POINTER(pz_star), C.POINTER(C.c_void_p)]
     lib.pz_batch_destroy.argtypes = [C.c_void_p]
     lib.pz_batch_destroy.restype = None
     lib.synth_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
-    for name in ("pz_plan_create", "pz_plan_info", "synth_forward", "synth_backward", "pz_line_opacity",
+    for name in ("pz_plan_create", "pz_plan_info", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
                  "pz_debug_formal_solve", "pz_batch_create", "synth_batch"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -106,7 +112,8 @@ def _load():
 lib = _load()
 
 EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "pz_plan_info",
-           "synth_forward", "synth_backward", "pz_line_opacity", "pz_debug_formal_solve",
+           "pz_plan_profile", "pz_plan_profile_read",
+           "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_formal_solve",
            "pz_batch_create", "pz_batch_destroy", "synth_batch")
 
 
@@ -163,6 +170,17 @@ class Plan:
         ev = C.c_int64()
         _check(lib.pz_plan_info(self.handle, *[C.byref(x) for x in v], C.byref(ev)))
         return tuple(x.value for x in v) + (ev.value,)
+
+    def profile(self, enable=True):
+        """pz_plan_profile: record hipEvents around this plan's kernel launches."""
+        _check(lib.pz_plan_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """pz_plan_profile_read -> {stage: (total_ms, launches)}."""
+        ms = (C.c_double * PZ_N_STAGES)()
+        n = (C.c_int32 * PZ_N_STAGES)()
+        _check(lib.pz_plan_profile_read(self.handle, ms, n))
+        return {STAGES[k]: (ms[k], n[k]) for k in range(PZ_N_STAGES)}
 
     def destroy(self):
         if getattr(self, "handle", None):
@@ -225,6 +243,11 @@ def synth_backward(plan, atm, par, dL_dF, g_loggf, g_damp, g_abund, g_xi, dL_dFc
 
 def pz_line_opacity(plan, atm, par, kappa, stream=None):
     _check(lib.pz_line_opacity(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(kappa), _stream(stream)))
+
+
+def pz_chi2_seed(F, Fc, y, sigma, dL_dF, dL_dFc=None, loss=None, stream=None):
+    _check(lib.pz_chi2_seed(int(F.numel()), _ptr(F), _ptr(Fc), _ptr(y), float(sigma), _ptr(dL_dF), _ptr(dL_dFc),
+                            _ptr(loss), _stream(stream)))
 
 
 def pz_debug_formal_solve(S, tau, F, quadrature=PZ_QUAD_GAUSS3, stream=None):

@@ -294,8 +294,51 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
 void pz_plan_destroy(pz_plan* plan) {
     if (!plan) return;
     (void)hipDeviceSynchronize();
+    if (plan->prof_ev) {
+        for (int k = 0; k < PZ_N_STAGES * PZ_PROFILE_SLOTS * 2; ++k) (void)hipEventDestroy(plan->prof_ev[k]);
+        delete[] plan->prof_ev;
+    }
     (void)hipFree(plan->base);
     delete plan;
+}
+
+int pz_plan_profile(pz_plan* plan, int32_t enable) {
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    if (enable && !plan->prof_ev) {
+        const int n = PZ_N_STAGES * PZ_PROFILE_SLOTS * 2;
+        plan->prof_ev = new (std::nothrow) hipEvent_t[n];
+        if (!plan->prof_ev) return fail(PZ_E_NOMEM, "host allocation failed");
+        for (int k = 0; k < n; ++k) {
+            hipError_t e = hipEventCreate(&plan->prof_ev[k]);
+            if (e != hipSuccess) {
+                for (int q = 0; q < k; ++q) (void)hipEventDestroy(plan->prof_ev[q]);
+                delete[] plan->prof_ev;
+                plan->prof_ev = nullptr;
+                return hip_fail(e, "hipEventCreate");
+            }
+        }
+    }
+    plan->prof = enable != 0;
+    if (enable)
+        for (int k = 0; k < PZ_N_STAGES; ++k) plan->prof_n[k] = 0;
+    return PZ_OK;
+}
+
+int pz_plan_profile_read(pz_plan* plan, double* total_ms, int32_t* count) {
+    if (!plan || !total_ms || !count) return fail(PZ_E_INVALID_ARG, "plan, total_ms and count are required");
+    for (int k = 0; k < PZ_N_STAGES; ++k) {
+        total_ms[k] = 0.0;
+        count[k] = plan->prof_ev ? plan->prof_n[k] : 0;
+        for (int q = 0; q < count[k]; ++q) {
+            hipEvent_t a = plan->prof_ev[(k * PZ_PROFILE_SLOTS + q) * 2];
+            hipEvent_t b = plan->prof_ev[(k * PZ_PROFILE_SLOTS + q) * 2 + 1];
+            PZ_HIP(hipEventSynchronize(b));
+            float ms = 0.0f;
+            PZ_HIP(hipEventElapsedTime(&ms, a, b));
+            total_ms[k] += ms;
+        }
+    }
+    return PZ_OK;
 }
 
 int pz_plan_info(const pz_plan* plan, int32_t* N, int32_t* L, int32_t* S, int32_t* D, int32_t* tile_px,
@@ -376,10 +419,36 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     return s;
 }
 
+// Bracket one stage launch with profiling events when enabled.
+struct StageTimer {
+    pz_plan* p;
+    int stage, slot;
+    hipStream_t st;
+    StageTimer(const pz_plan* plan, int stage_, hipStream_t st_)
+        : p(const_cast<pz_plan*>(plan)), stage(stage_), slot(-1), st(st_) {
+        if (p->prof && p->prof_n[stage] < PZ_PROFILE_SLOTS) {
+            slot = p->prof_n[stage]++;
+            (void)hipEventRecord(p->prof_ev[(stage * PZ_PROFILE_SLOTS + slot) * 2], st);
+        }
+    }
+    ~StageTimer() {
+        if (slot >= 0) (void)hipEventRecord(p->prof_ev[(stage * PZ_PROFILE_SLOTS + slot) * 2 + 1], st);
+    }
+};
+
 int enqueue_opacity(const pz_plan* p, const StarDev& s, hipStream_t st) {
-    PZ_HIP(launch_populations(s, st));
-    PZ_HIP(launch_line_params(s, st));
-    PZ_HIP(launch_opacity(s, p->chunk, st));
+    {
+        StageTimer t(p, PZ_STAGE_POPULATIONS, st);
+        PZ_HIP(launch_populations(s, st));
+    }
+    {
+        StageTimer t(p, PZ_STAGE_LINE_PARAMS, st);
+        PZ_HIP(launch_line_params(s, st));
+    }
+    {
+        StageTimer t(p, PZ_STAGE_OPACITY, st);
+        PZ_HIP(launch_opacity(s, p->chunk, st));
+    }
     return PZ_OK;
 }
 
@@ -400,6 +469,7 @@ int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par
     s.Fc = Fc;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    StageTimer t(plan, PZ_STAGE_FLUX, st);
     PZ_HIP(launch_flux(s, st));
     return PZ_OK;
 }
@@ -422,8 +492,15 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
     s.g_xi = g_xi;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = enqueue_opacity(plan, s, st))) return rc;
-    PZ_HIP(launch_reverse_scan(s, st));
-    PZ_HIP(launch_gather(s, st));
+    {
+        StageTimer t(plan, PZ_STAGE_REVERSE_SCAN, st);
+        PZ_HIP(launch_reverse_scan(s, st));
+    }
+    {
+        StageTimer t(plan, PZ_STAGE_GATHER, st);
+        PZ_HIP(launch_gather(s, st));
+    }
+    StageTimer t(plan, PZ_STAGE_REDUCE, st);
     PZ_HIP(launch_reduce(s, st));
     return PZ_OK;
 }
@@ -441,6 +518,16 @@ int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* p
     if ((rc = enqueue_opacity(plan, s, st))) return rc;
     PZ_HIP(hipMemcpy2DAsync(kappa_line, (size_t)plan->N * 4, plan->kappa, (size_t)plan->Npad * 4,
                             (size_t)plan->N * 4, plan->D, hipMemcpyDeviceToDevice, st));
+    return PZ_OK;
+}
+
+int pz_chi2_seed(int32_t N, const float* F, const float* Fc, const float* y, float sigma, float* dL_dF,
+                 float* dL_dFc, float* loss, pz_stream stream) {
+    g_err.clear();
+    if (N < 1) return fail(PZ_E_SHAPE, "N must be >= 1");
+    if (!F || !Fc || !y || !dL_dF) return fail(PZ_E_INVALID_ARG, "F, Fc, y and dL_dF are required");
+    if (!(sigma > 0.0f) || !std::isfinite(sigma)) return fail(PZ_E_INVALID_ARG, "sigma must be finite and > 0");
+    PZ_HIP(launch_chi2_seed(N, F, Fc, y, sigma, dL_dF, dL_dFc, loss, (hipStream_t)stream));
     return PZ_OK;
 }
 

@@ -90,6 +90,8 @@ hipError_t launch_flux(const StarDev& s, hipStream_t st);
 hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st);
 hipError_t launch_gather(const StarDev& s, hipStream_t st);
 hipError_t launch_reduce(const StarDev& s, hipStream_t st);
+hipError_t launch_chi2_seed(int N, const float* F, const float* Fc, const float* y, float sigma, float* gF,
+                            float* gFc, float* loss, hipStream_t st);
 hipError_t launch_debug_formal(int D, int n, const float* S, const float* tau, float* F,
                                hipStream_t st);
 
@@ -112,4 +114,8 @@ struct pz_plan {
     float* gk;
     float* gline;
     void* base;          // single device allocation holding everything above
+    // stage profiling (see pz_plan_profile)
+    bool prof;
+    int prof_n[PZ_N_STAGES];
+    hipEvent_t* prof_ev;  // [PZ_N_STAGES][PZ_PROFILE_SLOTS][2], created on first enable
 };

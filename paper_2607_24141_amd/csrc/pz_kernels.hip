@@ -168,9 +168,12 @@ __global__ __launch_bounds__(256) void k_opacity(StarDev s, int chunk) {
 //   I_D = S_{D-1} + mu (S_{D-1} - S_{D-2}) / (tau_{D-1} - tau_{D-2}).
 // This is the bottom-up recurrence of the formal solution unrolled into a
 // sum, so a single top-down pass with O(1) state per ray suffices.
-__constant__ float c_mu[3] = {0.11270166537925831f, 0.5f, 0.88729833462074169f};
-__constant__ float c_inv_mu[3] = {8.872983346207417f, 2.0f, 1.1270166537925831f};
-__constant__ float c_wmu[3] = {0.19669598484590563f, 1.3962634015954636f, 1.5487974519734657f};  // 2 pi w_k mu_k
+// 3-point Gauss-Legendre on [0, 1]: mu = 1/2 -+ sqrt(3/5)/2, 1/2; w = 5/18, 8/18, 5/18
+static constexpr double kMu0 = 0.1127016653792583, kMu1 = 0.5, kMu2 = 0.8872983346207417;
+__constant__ float c_mu[3] = {(float)kMu0, (float)kMu1, (float)kMu2};
+__constant__ float c_inv_mu[3] = {(float)(1.0 / kMu0), (float)(1.0 / kMu1), (float)(1.0 / kMu2)};
+__constant__ float c_wmu[3] = {(float)(2.0 * PI * 5.0 / 18.0 * kMu0), (float)(2.0 * PI * 8.0 / 18.0 * kMu1),
+                               (float)(2.0 * PI * 5.0 / 18.0 * kMu2)};  // 2 pi w_k mu_k
 
 struct ExpTerms {
     float e, om, lw, dlw;   // e^-x, 1 - e^-x, lw(x), lw'(x)
@@ -502,6 +505,37 @@ __global__ __launch_bounds__(256) void k_reduce_species_xi(StarDev s) {
     }
 }
 
+// ------------------------------------------------------------- loss seed
+// f = F/Fc, r = 2 (f - y)/sigma^2: dL/dF = r/Fc, dL/dFc = -r F/Fc^2.
+__global__ void k_chi2_seed(int N, const float* F, const float* Fc, const float* y, float inv_s2, float* gF,
+                            float* gFc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float inv_c = 1.0f / Fc[i];
+    const float f = F[i] * inv_c;
+    const float r = 2.0f * (f - y[i]) * inv_s2;
+    gF[i] = r * inv_c;
+    if (gFc) gFc[i] = -r * f * inv_c;
+}
+
+// Single-block fixed-order sum of ((f - y)/sigma)^2.
+__global__ __launch_bounds__(1024) void k_chi2_loss(int N, const float* F, const float* Fc, const float* y,
+                                                    float inv_s2, float* loss) {
+    __shared__ float red[1024];
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < N; i += 1024) {
+        const float d = F[i] / Fc[i] - y[i];
+        acc = fmaf(d * d, inv_s2, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0];
+}
+
 // ------------------------------------------------------------- launchers
 hipError_t launch_populations(const StarDev& s, hipStream_t st) {
     const int n = s.S * s.D;
@@ -546,6 +580,14 @@ hipError_t launch_gather(const StarDev& s, hipStream_t st) {
 hipError_t launch_reduce(const StarDev& s, hipStream_t st) {
     if (s.L > 0) k_scatter_lines<<<(s.L + 255) / 256, 256, 0, st>>>(s);
     k_reduce_species_xi<<<s.S + 1, 256, 0, st>>>(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi2_seed(int N, const float* F, const float* Fc, const float* y, float sigma, float* gF,
+                            float* gFc, float* loss, hipStream_t st) {
+    const float inv_s2 = 1.0f / (sigma * sigma);
+    k_chi2_seed<<<(N + 255) / 256, 256, 0, st>>>(N, F, Fc, y, inv_s2, gF, gFc);
+    if (loss) k_chi2_loss<<<1, 1024, 0, st>>>(N, F, Fc, y, inv_s2, loss);
     return hipGetLastError();
 }
 

@@ -1,0 +1,117 @@
+"""GPU vector-Jacobian product (Sec. 6, Eq. 30 corrections) against the FP64
+oracle adjoint with the identical seed, through the C ABI.
+
+Gradient tolerance (1e-3 relative): an entry passes iff
+|g - g_ref| <= 1e-3 |g_ref| where |g_ref| >= 1e-2 max|g_ref|, and
+|g - g_ref| <= 1e-5 max|g_ref| for the smaller entries (near-zero gradients
+carry no relative precision in float32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import synth as O
+
+pytestmark = pytest.mark.gpu
+
+
+def grad_close(got, ref, rtol=1e-3, name=""):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.max(np.abs(ref))
+    if scale == 0:
+        assert np.max(np.abs(got)) == 0, name
+        return 0.0
+    big = np.abs(ref) >= 1e-2 * scale
+    err_big = np.abs(got - ref)[big] / np.abs(ref[big])
+    err_small = np.abs(got - ref)[~big] / scale
+    assert err_big.max(initial=0) <= rtol, (name, err_big.max(), np.flatnonzero(big)[np.argmax(err_big)])
+    assert err_small.max(initial=0) <= 1e-5, (name, err_small.max())
+    return float(err_big.max(initial=0))
+
+
+def gpu_vjp(pz, wl, seed, plan=None):
+    plan = plan or pz.plan_for(wl)
+    atm = pz.Atmos(wl.atm)
+    par = pz.Params.from_host(wl.params)
+    s = torch.as_tensor(np.asarray(seed, np.float32), device="cuda")
+    g = [torch.full((plan.L,), np.nan, device="cuda"), torch.full((plan.L,), np.nan, device="cuda"),
+         torch.full((plan.S,), np.nan, device="cuda"), torch.full((1,), np.nan, device="cuda")]
+    print("synth_backward", wl.name, plan.N, plan.L, flush=True)
+    pz.synth_backward(plan, atm, par, s, *g)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy().astype(np.float64) for x in g]
+
+
+@pytest.mark.parametrize("seed,L,N,D,xi", [(21, 10, 350, 10, 1.4), (22, 60, 900, 72, 0.0), (23, 35, 513, 8, 2.5)])
+def test_vjp_tiny_vs_oracle(gpu_lib, seed, L, N, D, xi):
+    wl = W.tiny(seed=seed, L=L, N=N, D=D, S=4, n_molecular=1, xi=xi)
+    rng = np.random.default_rng(seed)
+    wl.params = W.random_params(rng, L, 4, xi)
+    s = rng.normal(size=N).astype(np.float32)
+    g = gpu_vjp(gpu_lib, wl, s)
+    ref = O.adjoint(wl, wl.params, s.astype(np.float64))
+    grad_close(g[0], ref["g_loggf"], name="loggf")
+    grad_close(g[1], ref["g_damp"], name="damp")
+    grad_close(g[2], ref["g_abund"], name="abund")
+    if xi > 0:
+        grad_close(g[3], [ref["g_xi"]], name="xi")
+    else:
+        assert abs(g[3][0]) <= 1e-5 * np.max(np.abs(ref["g_loggf"])) + 1e-30
+
+
+def test_vjp_abundance_is_species_sum(gpu_lib):
+    """dL/d dA_s equals the sum of dL/d dgf over the lines of species s (fixed atmosphere)."""
+    wl = W.tiny(seed=31, L=80, N=1200, D=72, S=5, n_molecular=1)
+    s = np.random.default_rng(1).normal(size=wl.grid.N).astype(np.float32)
+    g = gpu_vjp(gpu_lib, wl, s)
+    for sp in range(wl.atm.S):
+        tot = g[0][wl.lines.species == sp].sum()
+        assert abs(g[2][sp] - tot) <= 1e-5 * (np.abs(g[0][wl.lines.species == sp]).sum() + 1e-30)
+
+
+def test_vjp_deterministic(gpu_lib):
+    wl = W.tiny(seed=32, L=100, N=1500, D=72)
+    plan = gpu_lib.plan_for(wl)
+    s = np.random.default_rng(2).normal(size=wl.grid.N).astype(np.float32)
+    a = gpu_vjp(gpu_lib, wl, s, plan)
+    b = gpu_vjp(gpu_lib, wl, s, plan)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_chi2_seed_kernel(gpu_lib):
+    rng = np.random.default_rng(3)
+    N = 5000
+    Fc = rng.uniform(1e6, 2e6, N).astype(np.float32)
+    F = (Fc * rng.uniform(0.2, 1.0, N)).astype(np.float32)
+    y = (F / Fc + rng.normal(0, 0.01, N)).astype(np.float32)
+    t = lambda a: torch.as_tensor(a, device="cuda")
+    gF, gFc, loss = torch.empty(N, device="cuda"), torch.empty(N, device="cuda"), torch.empty(1, device="cuda")
+    gpu_lib.pz_chi2_seed(t(F), t(Fc), t(y), 0.01, gF, gFc, loss)
+    torch.cuda.synchronize()
+    rF, rFc = O.chi2_seed(F.astype(np.float64), Fc.astype(np.float64), y.astype(np.float64), 0.01)
+    f = F.astype(np.float64) / Fc
+    rl = np.sum(((f - y) / 0.01) ** 2)
+    # the residual f - y is ~1e-2 while f carries float32 rounding ~6e-8
+    np.testing.assert_allclose(gF.cpu().numpy(), rF, rtol=1e-4, atol=1e-4 * np.abs(rF).max())
+    np.testing.assert_allclose(gFc.cpu().numpy(), rFc, rtol=1e-4, atol=1e-4 * np.abs(rFc).max())
+    assert abs(loss.item() / rl - 1) < 1e-4
+
+
+def test_autograd_function(gpu_lib):
+    """torch.autograd through PzSynth gives the synth_backward gradients."""
+    wl = W.tiny(seed=33, L=30, N=600, D=72)
+    plan = gpu_lib.plan_for(wl)
+    atm = gpu_lib.Atmos(wl.atm)
+    dgf = torch.zeros(plan.L, device="cuda", requires_grad=True)
+    ddamp = torch.zeros(plan.L, device="cuda", requires_grad=True)
+    dA = torch.zeros(plan.S, device="cuda", requires_grad=True)
+    xi = torch.tensor([1.0], device="cuda", requires_grad=True)
+    F, Fc = gpu_lib.PzSynth().apply(plan, atm, dgf, ddamp, dA, xi)
+    w = torch.as_tensor(np.random.default_rng(4).normal(size=plan.N).astype(np.float32), device="cuda")
+    (F * w).sum().backward()
+    g = gpu_vjp(gpu_lib, wl, w.cpu().numpy(), plan)
+    np.testing.assert_array_equal(dgf.grad.cpu().numpy(), g[0])
+    np.testing.assert_array_equal(xi.grad.cpu().numpy(), g[3])
