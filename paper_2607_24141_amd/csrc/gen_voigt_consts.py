@@ -1,19 +1,32 @@
 """Writes voigt_consts.h: constants of the device Voigt evaluator.
 
-* Wing (|z| >= 5.5): 6-point Gauss-Hermite quadrature of the Voigt integral,
-  H(a,v) = (a/pi) int exp(-t^2)/((v-t)^2+a^2) dt, with the +/-t_k node pairs
-  combined so that every term is positive:
+Regions of z = v + i a (float32 unless noted):
+
+* wing, |z| >= 5.5: Gauss-Hermite quadrature of the Voigt integral
+  H(a,v) = (a/pi) int exp(-t^2)/((v-t)^2+a^2) dt with the +/-t_k node pairs
+  combined so every term is positive,
       H ~= (2a/pi) sum_k w_k (u + a^2 + t_k^2) / ((u - a^2 - t_k^2)^2 + 4 u a^2),
-  u = v^2.  Nodes from numpy's Gauss-Hermite rule.
-* Core (|z| < 5.5): Weideman's rational expansion of the Faddeeva function
-  (J.A.C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497), N = 32 terms,
-  coefficients from the FFT of exp(-t^2)(L^2+t^2) sampled at t = L tan(theta/2).
+  u = v^2.  Three tiers: 6 nodes for 5.5 <= |z| < 8, 4 nodes for
+  8 <= |z| < 40, 2 nodes beyond (max relative error ~1.4e-6 in each).
+* core with small damping, |z| < 5.5 and a <= 0.15: the expansion of
+  w(v + ia) in powers of a about the real axis,
+      w = exp(-z^2) + (2i/sqrt(pi)) F(z),   F = Dawson's integral,
+      H = exp(a^2-u) cos(2av) - (2/sqrt(pi)) [a F' - a^3 F'''/6 + a^5 F^(5)/120]
+      L = -exp(a^2-u) sin(2av) + (2/sqrt(pi)) [F - a^2 F''/2 + a^4 F''''/24],
+  with each derivative of F (even ones divided by v) replaced by a rational
+  function of u fitted here on [0, 30.25]; reference values from mpmath at
+  40 digits.  The Gaussian part carries the exact real-axis value, so H keeps
+  its relative accuracy where exp(-v^2) and the damping term are comparable.
+* core with larger damping: Weideman's 32-term rational expansion of w(z)
+  (J.A.C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497) in float64.
 
 Run:  python gen_voigt_consts.py > voigt_consts.h
 """
 import numpy as np
 
 N_W = 32
+U_MAX = 30.25
+A_SMALL = 0.15
 
 
 def weideman(N):
@@ -26,17 +39,122 @@ def weideman(N):
     return L, a[1:N + 1][::-1]          # highest power first (Horner order)
 
 
+def dawson_derivs(v):
+    """F, F', ..., F^(5) of Dawson's integral at v (mpmath, 40 digits)."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    out = np.zeros((6, len(v)))
+    for i, x in enumerate(v):
+        x = mp.mpf(x)
+        F0 = mp.sqrt(mp.pi) / 2 * mp.exp(-x * x) * mp.erfi(x)
+        d = [F0, 1 - 2 * x * F0]
+        for n in range(1, 5):          # F^(n+1) = -2 v F^(n) - 2 n F^(n-1)
+            d.append(-2 * x * d[n] - 2 * n * d[n - 1])
+        out[:, i] = [float(y) for y in d]
+    return out
+
+
+def ratfit(u, f, m, n, wt, iters=40):
+    """P/Q (deg m, n; Q(0) = 1) minimising the weighted max error (SK + Lawson)."""
+    Qp = np.ones_like(u)
+    w2 = np.ones_like(u)
+    for _ in range(iters):
+        A = np.hstack([np.vstack([u ** k for k in range(m + 1)]).T,
+                       -(f[:, None]) * np.vstack([u ** k for k in range(1, n + 1)]).T])
+        W = (wt * w2 / Qp)[:, None]
+        c, *_ = np.linalg.lstsq(A * W, f * W[:, 0], rcond=None)
+        p, q = c[:m + 1], np.concatenate([[1.0], c[m + 1:]])
+        P, Q = np.polyval(p[::-1], u), np.polyval(q[::-1], u)
+        err = np.abs((P / Q - f) * wt)
+        Qp = Q
+        w2 = w2 * (err / err.max()) ** 0.3 + 1e-12
+        w2 /= w2.max()
+    return p, q, err.max()
+
+
+def horner32(c, u):
+    r = np.zeros_like(u, dtype=np.float32)
+    for x in c[::-1].astype(np.float32):
+        r = r * u.astype(np.float32) + x
+    return r
+
+
+def fit_fixed_q(u, f, q, m, wt, iters=30):
+    """Numerator of degree m for a given denominator q, minimising the weighted max error."""
+    Q = np.polyval(q[::-1], u)
+    A = np.vstack([u ** j for j in range(m + 1)]).T
+    w2 = np.ones_like(u)
+    for _ in range(iters):
+        W = (wt / Q * w2)[:, None]
+        c, *_ = np.linalg.lstsq(A * W, f * Q * W[:, 0], rcond=None)
+        err = np.abs((A @ c / Q - f) * wt)
+        w2 = w2 * (err / err.max()) ** 0.3 + 1e-12
+        w2 /= w2.max()
+    return c, err.max()
+
+
+def fits():
+    """Common-denominator fits: Lam_k = P_k / Q (H terms), Mu_k = R_k / S (L terms)."""
+    v = np.linspace(0.0, np.sqrt(U_MAX), 1501)
+    u = v * v
+    F = dawson_derivs(v)
+    sp = 2.0 / np.sqrt(np.pi)
+    vv = np.where(v > 0, v, 1.0)
+    lam = [-sp * F[1], sp * F[3] / 6.0, -sp * F[5] / 120.0]
+    # odd derivatives divided by v, with their limits at v = 0 (1, -4, 32)
+    mu0 = np.where(v > 0, F[0] / vv, 1.0)
+    mu2 = np.where(v > 0, F[2] / vv, -4.0)
+    mu4 = np.where(v > 0, F[4] / vv, 32.0)
+    mus = [sp * mu0, -sp * mu2 / 2.0, sp * mu4 / 24.0]
+    a = A_SMALL
+    H = np.exp(a * a - u) * np.cos(2 * a * v) + a * (lam[0] + a * a * lam[1] + a ** 4 * lam[2])
+    res = {}
+    p0, q, e0 = ratfit(u, lam[0], 7, 8, a / H)
+    res["LAM_Q"] = (q, 0.0)
+    res["LAM_P0"] = (p0, e0)
+    for k, m in ((1, 8), (2, 7)):
+        c, e = fit_fixed_q(u, lam[k], q, m, a ** (2 * k + 1) / H)
+        res["LAM_P%d" % (2 * k)] = (c, e)
+    Lref = np.abs(-np.exp(a * a - u) * np.sin(2 * a * v) + v * (mus[0] + a * a * mus[1] + a ** 4 * mus[2]))
+    Lw = np.maximum(v, 1e-3) / np.maximum(Lref, 0.05)
+    r0, sq, e0 = ratfit(u, mus[0], 6, 7, Lw)
+    res["MU_Q"] = (sq, 0.0)
+    res["MU_P0"] = (r0, e0)
+    for k, m in ((1, 7), (2, 6)):
+        c, e = fit_fixed_q(u, mus[k], sq, m, a ** (2 * k) * Lw)
+        res["MU_P%d" % (2 * k)] = (c, e)
+    # float32 check of the assembled small-damping H at a = A_SMALL
+    f32 = np.float32
+    Qv = horner32(res["LAM_Q"][0], u)
+    num = horner32(res["LAM_P0"][0], u) + f32(a * a) * (horner32(res["LAM_P2"][0], u) +
+                                                         f32(a * a) * horner32(res["LAM_P4"][0], u))
+    H32 = np.exp(a * a - u) * np.cos(2 * a * v) + a * (num / Qv).astype(np.float64)
+    res["check_H"] = np.max(np.abs(H32 - H) / H)
+    return res
+
+
+def arr(name, c, typ="float", fmt="%.9ef"):
+    return "__device__ static constexpr %s %s[%d] = {%s};" % (typ, name, len(c), ", ".join(fmt % x for x in c))
+
+
 def main():
-    t, w = np.polynomial.hermite.hermgauss(6)
-    pos = t > 0
-    t2 = t[pos] ** 2
-    wk = w[pos] * 2.0 / np.pi
-    L, c = weideman(N_W)
     out = ["// Generated by gen_voigt_consts.py -- do not edit.", "#pragma once", ""]
-    out.append("#define PZ_VOIGT_WING_R2 30.25f   /* (5.5)^2: wing formula for v^2 + a^2 >= R^2 */")
-    out.append("static constexpr int PZ_GH_PAIRS = %d;" % len(t2))
-    out.append("__device__ static constexpr float PZ_GH_T2[%d] = {%s};" % (len(t2), ", ".join("%.9ef" % x for x in t2)))
-    out.append("__device__ static constexpr float PZ_GH_W[%d] = {%s};  /* w_k * 2/pi */" % (len(wk), ", ".join("%.9ef" % x for x in wk)))
+    out.append("#define PZ_VOIGT_WING_R2 30.25f   /* |z|^2 below which the core formulas apply */")
+    out.append("#define PZ_VOIGT_TIER2_R2 64.0f   /* |z| >= 8: four-node wing */")
+    out.append("#define PZ_VOIGT_TIER3_R2 1600.0f /* |z| >= 40: two-node wing */")
+    out.append("#define PZ_VOIGT_A_SMALL %.2ff      /* a <= this: float32 small-damping core */" % A_SMALL)
+    for n, tag in ((6, "GH6"), (4, "GH4"), (2, "GH2")):
+        t, w = np.polynomial.hermite.hermgauss(n)
+        pos = t > 0
+        out.append(arr("PZ_%s_T2" % tag, t[pos] ** 2))
+        out.append(arr("PZ_%s_W" % tag, w[pos] * 2.0 / np.pi) + "  /* w_k * 2/pi */")
+    res = fits()
+    out.append("/* small-damping core: max relative error of H at a = %.2f vs the truncated series: %.1e */"
+               % (A_SMALL, res["check_H"]))
+    for name in ("LAM_Q", "LAM_P0", "LAM_P2", "LAM_P4", "MU_Q", "MU_P0", "MU_P2", "MU_P4"):
+        c, e = res[name]
+        out.append(arr("PZ_%s" % name, c) + ("  /* weighted max error %.1e */" % e if e else ""))
+    L, c = weideman(N_W)
     out.append("static constexpr int PZ_WEID_N = %d;" % N_W)
     out.append("#define PZ_WEID_L %.17e" % L)
     out.append("__device__ static constexpr double PZ_WEID_C[%d] = {" % N_W)

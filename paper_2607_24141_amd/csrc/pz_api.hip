@@ -119,8 +119,8 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     int tile_px = opts->tile_px ? opts->tile_px : 64;
     if (tile_px != 32 && tile_px != 64 && tile_px != 128)
         return fail(PZ_E_INVALID_ARG, "tile_px must be 0, 32, 64 or 128 (got %d)", opts->tile_px);
-    int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 32;
-    if (chunk < 1 || chunk > 32) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 32]");
+    int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 16;
+    if (chunk < 1 || chunk > 16) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 16]");
     if (opts->flags != 0) return fail(PZ_E_INVALID_ARG, "flags must be 0");
     const int L = lines->L, N = grid->N, S = n_species, D = n_depth;
     if (L > 0) {

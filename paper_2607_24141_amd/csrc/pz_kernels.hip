@@ -47,7 +47,7 @@ __global__ void k_populations(StarDev s) {
 //   dv = sqrt(2kT/m + xi^2),  dnu_D = dv / lambda_l
 //   a  = 10^ddamp (g_rad + g_S n_e + g_vdW n_pert) / (4 pi dnu_D)
 //   K  = (pi e^2/m_e c) n/(rho U) 10^(loggf+dgf) e^{-E/kT} (1 - e^{-h nu_l/kT}) / (sqrt(pi) dnu_D)
-// stored as (c/dv, a, K, d ln dnu_D / d xi per km/s); v = (lambda_l/lambda_i - 1) c/dv.
+// stored as (c/dv, a, K, a^2); v = (lambda_l/lambda_i - 1) c/dv.
 __global__ void k_line_params(StarDev s) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)s.L * s.D) return;
@@ -58,8 +58,7 @@ __global__ void k_line_params(StarDev s) {
     const int caller = s.ln.perm[l];
     const double xi = (double)s.xi[0] * 1.0e5;
     const double mass = s.mass[sp] * AMU_G;
-    const double dv2 = 2.0 * K_BOLTZ * T / mass + xi * xi;
-    const double dv = sqrt(dv2);
+    const double dv = sqrt(2.0 * K_BOLTZ * T / mass + xi * xi);
     const double lam = s.ln.lam_cm[l];
     double gam = exp10(s.ln.lgr[l]) + exp10(s.ln.lgs[l]) * s.ne[j] + exp10(s.ln.lgw[l]) * s.npert[j];
     if (s.ddamp) gam *= exp10((double)s.ddamp[caller]);
@@ -70,7 +69,7 @@ __global__ void k_line_params(StarDev s) {
     const double strength = line_const * s.pop[spion * s.D + j] * exp10(loggf) *
                             exp(-s.ln.E_eV[l] * EV_ERG / kT) * (-expm1(-H_PLANCK * C_LIGHT / (lam * kT)));
     const double K = strength * lam / (sqrt(PI) * dv);
-    s.lp[idx] = make_float4((float)(C_LIGHT / dv), (float)a, (float)K, (float)(xi * 1.0e5 / dv2));
+    s.lp[idx] = make_float4((float)(C_LIGHT / dv), (float)a, (float)K, (float)(a * a));
 }
 
 // x = lambda_l / lambda_i - 1 = expm1(delta - k h), k = i - ic: the
@@ -83,31 +82,36 @@ __device__ __forceinline__ float detuning(int k, float delta, float h_hi, float 
 }
 
 // -------------------------------------------------------------- opacity
-// One workgroup owns TP pixels x all depths; thread (px, dg) accumulates the
-// depths j = d * NDG + dg of pixel px in registers.  The lines overlapping the
-// tile form a contiguous range of the sorted list; their per-depth parameters
-// are staged through LDS in chunks.  No atomics: every (pixel, depth) sum is
-// owned by one thread and runs in sorted-line order.
-static constexpr int MAX_CHUNK = 32;
+// A workgroup of 8 wavefronts owns TPX = 8 WPX consecutive pixels x all
+// depths.  Each wavefront covers WPX pixels x NDG = 64/WPX depth groups, so
+// its lanes see nearby detunings (little divergence between the Voigt
+// regions) and a line's window edge masks few lanes.  Thread (px, dg)
+// accumulates depths j = d NDG + dg of its pixel in registers.  The lines
+// overlapping the tile are a contiguous range of the sorted list; their
+// per-depth parameters are staged through LDS in chunks.  No atomics: every
+// (pixel, depth) sum is owned by one thread and runs in sorted-line order.
+static constexpr int MAX_CHUNK = 16;
 
 struct alignas(16) LineLds {
     float delta;
     int ic, ilo, ihi;
 };
 
-template <int TP, int NDG>
-__global__ __launch_bounds__(256) void k_opacity(StarDev s, int chunk) {
-    static_assert(TP * NDG == 256, "block of 256 threads");
-    constexpr int DPT = MAXD / NDG;
+template <int WPX>
+__global__ __launch_bounds__(512) void k_opacity(StarDev s, int chunk) {
+    constexpr int NDG = 64 / WPX;
+    constexpr int DPT = (MAXD + NDG - 1) / NDG;
+    constexpr int TPX = 8 * WPX;
     __shared__ float4 s_lp[MAX_CHUNK * MAXD];
     __shared__ LineLds s_ln[MAX_CHUNK];
-    const int tile = blockIdx.x;
     const int tid = threadIdx.x;
-    const int px = tid % TP;
-    const int dg = tid / TP;
-    const int i = tile * TP + px;
+    const int lane = tid % 64;
+    const int px = lane % WPX;
+    const int dg = lane / WPX;
+    const int w0 = blockIdx.x * TPX + (tid / 64) * WPX;   // first pixel of this wavefront
+    const int i = w0 + px;
     const int D = s.D;
-    const int l0 = s.tile_first[tile], l1 = s.tile_last[tile];
+    const int l0 = s.tile_first[blockIdx.x], l1 = s.tile_last[blockIdx.x];
     float acc[DPT];
 #pragma unroll
     for (int d = 0; d < DPT; ++d) acc[d] = 0.0f;
@@ -115,17 +119,17 @@ __global__ __launch_bounds__(256) void k_opacity(StarDev s, int chunk) {
     for (int c0 = l0; c0 < l1; c0 += chunk) {
         const int nc = min(chunk, l1 - c0);
         const float4* src = s.lp + (size_t)c0 * D;
-        for (int k = tid; k < nc * D; k += 256) {
+        for (int k = tid; k < nc * D; k += 512) {
             const int q = k / D;
             s_lp[q * MAXD + (k - q * D)] = src[k];
         }
-        for (int q = tid; q < nc; q += 256) {
+        if (tid < nc) {
             LineLds t;
-            t.delta = s.ln.delta[c0 + q];
-            t.ic = s.ln.ic[c0 + q];
-            t.ilo = s.ln.ilo[c0 + q];
-            t.ihi = s.ln.ihi[c0 + q];
-            s_ln[q] = t;
+            t.delta = s.ln.delta[c0 + tid];
+            t.ic = s.ln.ic[c0 + tid];
+            t.ilo = s.ln.ilo[c0 + tid];
+            t.ihi = s.ln.ihi[c0 + tid];
+            s_ln[tid] = t;
         }
         __syncthreads();
         for (int q = 0; q < nc; ++q) {
@@ -139,8 +143,7 @@ __global__ __launch_bounds__(256) void k_opacity(StarDev s, int chunk) {
                     if (j < D) {
                         const float4 p = row[j];
                         const float v = x * p.x;
-                        const float u = v * v;
-                        acc[d] = fmaf(p.z, voigt_H(p.y, v, u), acc[d]);
+                        acc[d] = fmaf(p.z, voigt_H(p.y, p.w, v, v * v), acc[d]);
                     }
                 }
             }
@@ -422,11 +425,13 @@ __global__ __launch_bounds__(64) void k_reverse_scan(StarDev s) {
 }
 
 // -------------------------------------------------------- gather (adjoint)
-// One wavefront per line: lanes stride over the line's window pixels, the
-// depth loop is inner; the Voigt function and its derivatives are recomputed.
+// One wavefront per line: its lanes are 8 pixels x 8 depth groups and step
+// through the window 8 pixels at a time; the line's per-depth parameters stay
+// in registers.  The Voigt function and its derivatives are recomputed:
 //   dL/d dgf   = ln10 sum g K H
 //   dL/d ddamp = ln10 sum g K a dH/da
-//   dL/d xi    = sum g (-K) (H + a dH/da + v dH/dv) d ln dnu_D / d xi
+//   dL/d xi    = sum g (-K) (H + a dH/da + v dH/dv) d ln dnu_D / d xi,
+//   d ln dnu_D / d xi = xi / dv^2 = xi (s / c)^2 with s = c/dv  (per km/s: x 1e10)
 // A fixed-order butterfly reduces across lanes, so the sums are deterministic.
 __device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
@@ -435,27 +440,36 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 
 __global__ __launch_bounds__(256) void k_gather(StarDev s) {
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int l = blockIdx.x * (256 / WAVE) + wave;
+    constexpr int WPX = 8, NDG = 8, DPT = (MAXD + NDG - 1) / NDG;
+    const int lane = threadIdx.x % WAVE;
+    const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / WAVE) + (int)(threadIdx.x / WAVE));
     if (l >= s.L) return;
+    const int px = lane % WPX, dg = lane / WPX;
     const int ilo = s.ln.ilo[l], ihi = s.ln.ihi[l], ic = s.ln.ic[l];
     const float delta = s.ln.delta[l];
     const int D = s.D;
     const float4* lp = s.lp + (size_t)l * D;
+    const float xi_f = s.xi[0] * (float)(1.0e10 / (C_LIGHT * C_LIGHT));
     float sgf = 0.0f, sd = 0.0f, sxi = 0.0f;
-    for (int i = ilo + lane; i <= ihi; i += WAVE) {
-        const float x = detuning(i - ic, delta, s.h_hi, s.h_lo);
-        const float* g = s.gk + i;
-        for (int j = 0; j < D; ++j) {
-            const float4 p = lp[j];
-            const float gK = g[(size_t)j * s.Npad] * p.z;
-            const float v = x * p.x;
-            const float u = v * v;
-            float H, aHa, X;
-            voigt_HD(p.y, v, u, H, aHa, X);
-            sgf = fmaf(gK, H, sgf);
-            sd = fmaf(gK, aHa, sd);
-            sxi = fmaf(-gK * X, p.w, sxi);
+    for (int p0 = ilo; p0 <= ihi; p0 += WPX) {
+        const int i = p0 + px;
+        if (i <= ihi) {
+            const float x = detuning(i - ic, delta, s.h_hi, s.h_lo);
+            const float* g = s.gk + i;
+#pragma unroll 1
+            for (int d = 0; d < DPT; ++d) {
+                const int j = d * NDG + dg;
+                if (j < D) {
+                    const float4 q = lp[j];
+                    const float gK = g[(size_t)j * s.Npad] * q.z;
+                    const float v = x * q.x;
+                    float H, aHa, X;
+                    voigt_HD(q.y, q.w, v, v * v, H, aHa, X);
+                    sgf = fmaf(gK, H, sgf);
+                    sd = fmaf(gK, aHa, sd);
+                    sxi = fmaf(-gK * X, xi_f * q.x * q.x, sxi);
+                }
+            }
         }
     }
     sgf = wave_sum(sgf);
@@ -553,9 +567,9 @@ hipError_t launch_line_params(const StarDev& s, hipStream_t st) {
 hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
     if (s.n_tiles == 0) return hipSuccess;
     switch (s.tile_px) {
-        case 32: k_opacity<32, 8><<<s.n_tiles, 256, 0, st>>>(s, chunk); break;
-        case 64: k_opacity<64, 4><<<s.n_tiles, 256, 0, st>>>(s, chunk); break;
-        case 128: k_opacity<128, 2><<<s.n_tiles, 256, 0, st>>>(s, chunk); break;
+        case 32: k_opacity<4><<<s.n_tiles, 512, 0, st>>>(s, chunk); break;
+        case 64: k_opacity<8><<<s.n_tiles, 512, 0, st>>>(s, chunk); break;
+        case 128: k_opacity<16><<<s.n_tiles, 512, 0, st>>>(s, chunk); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
