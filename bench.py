@@ -192,38 +192,49 @@ def main():
                           "voigt_evals_per_s": 2 * plan.voigt_evals / (ms_fb * 1e-3),
                           "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof_fb.items() if v[1]}}
 
-    # ---- batched forward + backward over many stars
+    # ---- batched forward + backward over many stars (one captured graph)
     if "batch" in modes:
         nb = args.batch_stars
         log("generating %d-star batch" % nb)
         from concurrent.futures import ThreadPoolExecutor
-        stars_wl = [W.batch_star(b) for b in range(nb)]
         with ThreadPoolExecutor(16) as ex:
+            stars_wl = list(ex.map(W.batch_star, range(nb)))
             plans = list(ex.map(lambda w: pz.plan_for(w), stars_wl))
-        keep = []
-        descr = []
-        total_evals = 0
+        keep, descr, total_evals = [], [], 0
+        rng = np.random.default_rng(5)
         for w, p in zip(stars_wl, plans):
             a = pz.Atmos(w.atm)
             q = pz.Params.from_host(w.params)
             bufs = dict(F=torch.empty(p.N, device=dev), Fc=torch.empty(p.N, device=dev),
-                        seed=torch.randn(p.N, device=dev) * 1e-6,
+                        y=torch.as_tensor(rng.uniform(0.5, 1.0, p.N).astype(np.float32), device=dev),
+                        loss=torch.empty(1, device=dev),
                         gl=torch.empty(p.L, device=dev), gd=torch.empty(p.L, device=dev),
                         ga=torch.empty(p.S, device=dev), gx=torch.empty(1, device=dev))
             keep.append((a, q, bufs))
-            descr.append(pz.pz_star(p.handle.value, a.c, q.c, bufs["F"].data_ptr(), bufs["Fc"].data_ptr(),
-                                    bufs["seed"].data_ptr(), bufs["gl"].data_ptr(), bufs["gd"].data_ptr(),
-                                    bufs["ga"].data_ptr(), bufs["gx"].data_ptr()))
+            descr.append(pz.pz_star(p.handle.value, a.c, q.c, bufs["F"].data_ptr(), bufs["Fc"].data_ptr(), None,
+                                    bufs["y"].data_ptr(), 0.01, bufs["loss"].data_ptr(), bufs["gl"].data_ptr(),
+                                    bufs["gd"].data_ptr(), bufs["ga"].data_ptr(), bufs["gx"].data_ptr()))
             total_evals += p.voigt_evals
         batch = pz.Batch(descr)
         log("batch: %d stars, %.3e evals per forward" % (nb, total_evals))
+        graphs = {}
+        for mode in (pz.PZ_MODE_FWD, pz.PZ_MODE_FWD_BWD):
+            pz.synth_batch(batch, mode)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                pz.synth_batch(batch, mode)
+            graphs[mode] = g
         bsteps = max(2, args.steps // 4)
-        ms_bf, _ = timed(lambda: pz.synth_batch(batch, pz.PZ_MODE_FWD), bsteps, 1, torch)
-        ms_bb, _ = timed(lambda: pz.synth_batch(batch, pz.PZ_MODE_FWD_BWD), bsteps, 1, torch)
-        out["batched"] = {"stars": nb, "fwd_spectra_per_s": nb * 1000.0 / ms_bf, "fwd_ms": ms_bf,
+        ms_bf, _ = timed(graphs[pz.PZ_MODE_FWD].replay, bsteps, 1, torch)
+        ms_bb, _ = timed(graphs[pz.PZ_MODE_FWD_BWD].replay, bsteps, 1, torch)
+        out["batched"] = {"stars": nb, "hipgraph": True, "fwd_spectra_per_s": nb * 1000.0 / ms_bf, "fwd_ms": ms_bf,
                           "fwd_bwd_spectra_per_s": nb * 1000.0 / ms_bb, "fwd_bwd_ms": ms_bb,
                           "fwd_voigt_evals_per_s": total_evals / (ms_bf * 1e-3),
-                          "fwd_bwd_over_fwd": ms_bb / ms_bf}
+                          "fwd_bwd_over_fwd": ms_bb / ms_bf,
+                          "evals_per_fwd": total_evals,
+                          "pixels": int(sum(p.N for p in plans)), "lines": int(sum(p.L for p in plans))}
+        del graphs
         batch.destroy()
         for p in plans:
             p.destroy()

@@ -145,6 +145,10 @@ const char* pz_last_error(void);
 int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species,
                    int32_t n_depth, const pz_options* opts, pz_plan** out);
 
+/* Forget the workspace of the last forward pass, so the next synth_backward
+ * recomputes the opacity. */
+int pz_plan_invalidate(pz_plan* plan);
+
 /* Release a plan (NULL is a no-op).  Synchronises the device. */
 void pz_plan_destroy(pz_plan* plan);
 
@@ -164,8 +168,12 @@ int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par
  * dL/d dgf[L] and dL/d ddamp[L] (caller line order), dL/d dA[S] and
  * dL/d xi[1] (per km/s), all device float32.  dL_dFc may be NULL: the
  * continuum branch depends on none of the corrections, so it is ignored.
- * Recomputes the forward pass internally (same stream), so it does not depend
- * on an earlier synth_forward.  Any gradient pointer may be NULL to skip it. */
+ * The line opacity of the most recent synth_forward on this plan is reused
+ * when that call had the same atmosphere and correction descriptors (same
+ * pointers) and the same stream, and no other call has written the plan's
+ * workspace since; otherwise the forward opacity is recomputed first.  The
+ * caller must not change the contents of those arrays in between, or must
+ * call pz_plan_invalidate.  Any gradient pointer may be NULL to skip it. */
 int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
                    const float* dL_dF, const float* dL_dFc,
                    float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
@@ -215,7 +223,11 @@ typedef struct {
     pz_params par;
     float* F;                    /* [N]  */
     float* Fc;                   /* [N]  */
-    const float* dL_dF;          /* [N], FWD_BWD only */
+    const float* dL_dF;          /* [N], FWD_BWD seed when y is NULL */
+    const float* y;              /* [N] or NULL: chi^2 target (pz_chi2_seed); the seed
+                                    is then computed from this star's F and Fc */
+    float sigma;                 /* chi^2 noise level (used with y) */
+    float* loss;                 /* [1] or NULL: chi^2 value (used with y) */
     float* g_loggf;              /* [L], FWD_BWD only (may be NULL) */
     float* g_damp;               /* [L]  */
     float* g_abund;              /* [S]  */
@@ -223,16 +235,29 @@ typedef struct {
 } pz_star;
 
 /* Prepare a batch of stars with different atmospheres, windows and line
- * counts: uploads a device table of the stars' pointers and builds the work
- * queues (per-star plans must stay alive).  Synchronises the device. */
+ * counts: uploads a device table of the stars' descriptors and builds the
+ * work lists (opacity tiles of all stars ordered by decreasing cost).  The
+ * per-star plans must outlive the batch, and no two stars may share a plan
+ * (each plan's workspace holds that star's intermediate arrays).
+ * Synchronises the device. */
 int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out);
 void pz_batch_destroy(pz_batch* batch);
 
-/* Batched synthesis: all stars' work in persistent work-queue launches
- * (PZ_MODE_FWD or PZ_MODE_FWD_BWD).  Enqueue-only: no host synchronisation or
- * allocation, so it may be captured in a hipGraph.  Results are bitwise equal
- * to per-star synth_forward / synth_backward calls. */
+/* Batched synthesis (PZ_MODE_FWD or PZ_MODE_FWD_BWD): every stage runs as one
+ * persistent launch whose workgroups take (star, item) work from a queue
+ * spanning all stars.  Enqueue-only: no host synchronisation, allocation or
+ * memset, so the call may be captured in a hipGraph and replayed.  Results
+ * are bitwise equal to per-star synth_forward / pz_chi2_seed /
+ * synth_backward calls with the same plans. */
 int synth_batch(const pz_batch* batch, int32_t mode, pz_stream stream);
+
+/* Autotuner: times synth_forward for every supported (tile_px,
+ * lines_per_chunk) pair on the given inputs and returns the fastest in
+ * *best (other fields copied from *base).  Builds temporary plans and
+ * synchronises the device; reps timed forward passes per candidate. */
+int pz_autotune(const pz_grid* grid, const pz_lines* lines, int32_t n_species, int32_t n_depth,
+                const pz_options* base, const pz_atmos* atm, const pz_params* par, int32_t reps,
+                pz_options* best, float* best_ms);
 
 #ifdef __cplusplus
 }

@@ -66,7 +66,8 @@ class pz_params(C.Structure):
 
 class pz_star(C.Structure):
     _fields_ = [("plan", C.c_void_p), ("atm", pz_atmos), ("par", pz_params), ("F", C.c_void_p),
-                ("Fc", C.c_void_p), ("dL_dF", C.c_void_p), ("g_loggf", C.c_void_p), ("g_damp", C.c_void_p),
+                ("Fc", C.c_void_p), ("dL_dF", C.c_void_p), ("y", C.c_void_p), ("sigma", C.c_float),
+                ("loss", C.c_void_p), ("g_loggf", C.c_void_p), ("g_damp", C.c_void_p),
                 ("g_abund", C.c_void_p), ("g_xi", C.c_void_p)]
 
 
@@ -97,24 +98,28 @@ def _load():
                                           C.c_void_p, C.c_void_p]
     lib.pz_chi2_seed.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.pz_plan_invalidate.argtypes = [C.c_void_p]
     lib.pz_plan_profile.argtypes = [C.c_void_p, C.c_int32]
     lib.pz_plan_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), _c_int_p]
     lib.pz_batch_create.argtypes = [C.c_int32, C.POINTER(pz_star), C.POINTER(C.c_void_p)]
     lib.pz_batch_destroy.argtypes = [C.c_void_p]
     lib.pz_batch_destroy.restype = None
     lib.synth_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
-    for name in ("pz_plan_create", "pz_plan_info", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
-                 "pz_debug_formal_solve", "pz_batch_create", "synth_batch"):
+    lib.pz_autotune.argtypes = [C.POINTER(pz_grid), C.POINTER(pz_lines), C.c_int32, C.c_int32,
+                                C.POINTER(pz_options), C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_int32,
+                                C.POINTER(pz_options), C.POINTER(C.c_float)]
+    for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
+                 "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune"):
         getattr(lib, name).restype = C.c_int
     return lib
 
 
 lib = _load()
 
-EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "pz_plan_info",
+EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "pz_plan_info", "pz_plan_invalidate",
            "pz_plan_profile", "pz_plan_profile_read",
            "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_formal_solve",
-           "pz_batch_create", "pz_batch_destroy", "synth_batch")
+           "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune")
 
 
 def _check(rc):
@@ -139,29 +144,45 @@ def _stream(stream=None):
 
 
 # ----------------------------------------------------------------------- plan
+def c_grid_lines(grid, lines):
+    """pz_grid and pz_lines descriptors over contiguous host copies (kept alive by the caller)."""
+    keep = []
+
+    def d(arr, dt):
+        a = np.ascontiguousarray(arr, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(_c_double_p if dt == np.float64 else _c_int_p)
+
+    g = pz_grid(float(grid.lam_first_nm), float(grid.R), int(grid.N))
+    ln = pz_lines(int(len(lines.lam0_nm)), d(lines.lam0_nm, np.float64), d(lines.loggf, np.float64),
+                  d(lines.E_eV, np.float64), d(lines.species, np.int32), d(lines.ion, np.int32),
+                  d(lines.log_grad, np.float64), d(lines.log_gstark, np.float64), d(lines.log_gvdw, np.float64))
+    return g, ln, keep
+
+
+def pz_autotune(grid, lines, n_species, n_depth, atm, par, window_nm=0.3, reps=3):
+    """Fastest (tile_px, lines_per_chunk) for these inputs -> (tile_px, lines_per_chunk, ms)."""
+    g, ln, keep = c_grid_lines(grid, lines)
+    base = pz_options(float(window_nm), PZ_QUAD_GAUSS3, 0, 0, 0)
+    best = pz_options()
+    ms = C.c_float()
+    _check(lib.pz_autotune(C.byref(g), C.byref(ln), int(n_species), int(n_depth), C.byref(base), C.byref(atm.c),
+                           C.byref(par.c), int(reps), C.byref(best), C.byref(ms)))
+    del keep
+    return best.tile_px, best.lines_per_chunk, ms.value
+
+
 class Plan:
     """pz_plan_create / pz_plan_destroy around host line arrays (float64)."""
 
     def __init__(self, grid, lines, n_species, n_depth, window_nm=0.3, quadrature=PZ_QUAD_GAUSS3,
                  tile_px=0, lines_per_chunk=0, flags=0):
-        self._keep = {}
-        g = pz_grid(float(grid.lam_first_nm), float(grid.R), int(grid.N))
-
-        def d(name, arr, dt):
-            a = np.ascontiguousarray(arr, dtype=dt)
-            self._keep[name] = a
-            return a.ctypes.data_as(_c_double_p if dt == np.float64 else _c_int_p)
-
-        ln = pz_lines(int(len(lines.lam0_nm)), d("lam0", lines.lam0_nm, np.float64),
-                      d("loggf", lines.loggf, np.float64), d("E", lines.E_eV, np.float64),
-                      d("sp", lines.species, np.int32), d("ion", lines.ion, np.int32),
-                      d("gr", lines.log_grad, np.float64), d("gs", lines.log_gstark, np.float64),
-                      d("gw", lines.log_gvdw, np.float64))
+        g, ln, keep = c_grid_lines(grid, lines)
         opts = pz_options(float(window_nm), int(quadrature), int(tile_px), int(lines_per_chunk), int(flags))
         h = C.c_void_p()
         _check(lib.pz_plan_create(C.byref(g), C.byref(ln), int(n_species), int(n_depth), C.byref(opts),
                                   C.byref(h)))
-        self._keep.clear()
+        del keep
         self.handle = h
         self.N, self.L, self.S, self.D, self.tile_px, self.voigt_evals = self.info()
 
@@ -170,6 +191,10 @@ class Plan:
         ev = C.c_int64()
         _check(lib.pz_plan_info(self.handle, *[C.byref(x) for x in v], C.byref(ev)))
         return tuple(x.value for x in v) + (ev.value,)
+
+    def invalidate(self):
+        """pz_plan_invalidate: the next synth_backward recomputes the forward opacity."""
+        _check(lib.pz_plan_invalidate(self.handle))
 
     def profile(self, enable=True):
         """pz_plan_profile: record hipEvents around this plan's kernel launches."""

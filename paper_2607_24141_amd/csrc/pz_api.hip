@@ -211,13 +211,32 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
                  o_spo = take((size_t)(S + 1) * 4), o_spi = take(Ls * 4), o_pop = take((size_t)S * 2 * D * 8),
                  o_lp = take(Ls * D * 16), o_kap = take((size_t)D * Npad * 4), o_gk = take((size_t)D * Npad * 4),
                  o_gl = take(Ls * 3 * 4);
+    const int n_rchunk = (int)((Ls + RCHUNK - 1) / RCHUNK);
+    const size_t o_part = take((size_t)(S + 1) * n_rchunk * 4);
+    const size_t o_seed = take((size_t)Npad * 4);
+    // Voigt evaluations per tile (orders the batched opacity work)
+    std::vector<int64_t> tcost(n_tiles, 0);
+    for (int k = 0; k < L; ++k) {
+        if (ihi[k] < ilo[k]) continue;
+        for (int t = ilo[k] / tile_px; t <= ihi[k] / tile_px; ++t) {
+            const int a0 = std::max(ilo[k], t * tile_px), a1 = std::min(ihi[k], t * tile_px + tile_px - 1);
+            tcost[t] += (int64_t)(a1 - a0 + 1) * D;
+        }
+    }
     pz_plan* p = new (std::nothrow) pz_plan();
     if (!p) return fail(PZ_E_NOMEM, "host allocation failed");
     std::memset(p, 0, sizeof *p);
+    p->tile_cost = new (std::nothrow) int64_t[n_tiles];
+    if (!p->tile_cost) {
+        delete p;
+        return fail(PZ_E_NOMEM, "host allocation failed");
+    }
+    std::copy(tcost.begin(), tcost.end(), p->tile_cost);
     PZ_HIP(hipGetDevice(&p->device));
     char* base = nullptr;
     hipError_t e = hipMalloc((void**)&base, off);
     if (e != hipSuccess) {
+        delete[] p->tile_cost;
         delete p;
         (void)hipGetLastError();
         return fail(PZ_E_NOMEM, "hipMalloc of %zu bytes failed: %s", off, hipGetErrorString(e));
@@ -258,6 +277,9 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->kappa = (float*)(base + o_kap);
     p->gk = (float*)(base + o_gk);
     p->gline = (float*)(base + o_gl);
+    p->partial = (float*)(base + o_part);
+    p->n_rchunk = n_rchunk;
+    p->seed = (float*)(base + o_seed);
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
@@ -282,8 +304,10 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     if (ue == hipSuccess) ue = hipMemset(p->gk, 0, (size_t)D * Npad * 4);
     if (ue == hipSuccess) ue = hipMemset(p->gline, 0, Ls * 3 * 4);
     if (ue == hipSuccess) ue = hipDeviceSynchronize();
+    if (ue == hipSuccess) ue = hipMemset(p->seed, 0, (size_t)Npad * 4);
     if (ue != hipSuccess) {
         (void)hipFree(base);
+        delete[] p->tile_cost;
         delete p;
         return hip_fail(ue, "plan upload");
     }
@@ -299,7 +323,14 @@ void pz_plan_destroy(pz_plan* plan) {
         delete[] plan->prof_ev;
     }
     (void)hipFree(plan->base);
+    delete[] plan->tile_cost;
     delete plan;
+}
+
+int pz_plan_invalidate(pz_plan* plan) {
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    plan->ws_valid = false;
+    return PZ_OK;
 }
 
 int pz_plan_profile(pz_plan* plan, int32_t enable) {
@@ -357,6 +388,8 @@ int pz_plan_info(const pz_plan* plan, int32_t* N, int32_t* L, int32_t* S, int32_
 
 namespace pz {
 
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
 int check_atmos(const pz_plan* plan, const pz_atmos* atm) {
     if (!atm) return fail(PZ_E_INVALID_ARG, "atmosphere is NULL");
     if (atm->D != plan->D) return fail(PZ_E_SHAPE, "atmosphere has D=%d, plan expects %d", atm->D, plan->D);
@@ -386,6 +419,7 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.D = p->D;
     s.tile_px = p->tile_px;
     s.n_tiles = p->n_tiles;
+    s.chunk = p->chunk;
     s.lam_first_nm = p->lam_first_nm;
     s.h = p->h;
     s.h_hi = (float)p->h;
@@ -416,6 +450,8 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.kappa = p->kappa;
     s.gk = p->gk;
     s.gline = p->gline;
+    s.partial = p->partial;
+    s.n_rchunk = p->n_rchunk;
     return s;
 }
 
@@ -435,6 +471,19 @@ struct StageTimer {
         if (slot >= 0) (void)hipEventRecord(p->prof_ev[(stage * PZ_PROFILE_SLOTS + slot) * 2 + 1], st);
     }
 };
+
+void record_workspace(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, hipStream_t st) {
+    pz_plan* p = const_cast<pz_plan*>(plan);
+    p->ws_valid = true;
+    p->ws_atm = *atm;
+    p->ws_par = *par;
+    p->ws_stream = st;
+}
+
+bool workspace_matches(const pz_plan* p, const pz_atmos* atm, const pz_params* par, hipStream_t st) {
+    return p->ws_valid && p->ws_stream == st && std::memcmp(&p->ws_atm, atm, sizeof *atm) == 0 &&
+           std::memcmp(&p->ws_par, par, sizeof *par) == 0;
+}
 
 int enqueue_opacity(const pz_plan* p, const StarDev& s, hipStream_t st) {
     {
@@ -468,7 +517,9 @@ int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par
     s.F = F;
     s.Fc = Fc;
     hipStream_t st = (hipStream_t)stream;
+    const_cast<pz_plan*>(plan)->ws_valid = false;
     if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    record_workspace(plan, atm, par, st);
     StageTimer t(plan, PZ_STAGE_FLUX, st);
     PZ_HIP(launch_flux(s, st));
     return PZ_OK;
@@ -491,7 +542,11 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
     s.g_abund = g_abund;
     s.g_xi = g_xi;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    if (!workspace_matches(plan, atm, par, st)) {
+        const_cast<pz_plan*>(plan)->ws_valid = false;
+        if ((rc = enqueue_opacity(plan, s, st))) return rc;
+        record_workspace(plan, atm, par, st);
+    }
     {
         StageTimer t(plan, PZ_STAGE_REVERSE_SCAN, st);
         PZ_HIP(launch_reverse_scan(s, st));
@@ -515,7 +570,9 @@ int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* p
     if (!kappa_line) return fail(PZ_E_INVALID_ARG, "kappa_line is required");
     StarDev s = make_star(plan, atm, par);
     hipStream_t st = (hipStream_t)stream;
+    const_cast<pz_plan*>(plan)->ws_valid = false;
     if ((rc = enqueue_opacity(plan, s, st))) return rc;
+    record_workspace(plan, atm, par, st);
     PZ_HIP(hipMemcpy2DAsync(kappa_line, (size_t)plan->N * 4, plan->kappa, (size_t)plan->Npad * 4,
                             (size_t)plan->N * 4, plan->D, hipMemcpyDeviceToDevice, st));
     return PZ_OK;

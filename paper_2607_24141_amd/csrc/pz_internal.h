@@ -41,7 +41,7 @@ struct LineArrays {
 // outputs + workspaces).  Passed by value or stored in the batch table.
 struct StarDev {
     // grid
-    int N, Npad, L, S, D, tile_px, n_tiles;
+    int N, Npad, L, S, D, tile_px, n_tiles, chunk;
     double lam_first_nm, h;      // h = ln(1 + 1/R)
     float h_hi, h_lo;            // h split for float32 offsets
     LineArrays ln;
@@ -79,7 +79,11 @@ struct StarDev {
     float* kappa;                // [D][Npad]
     float* gk;                   // [D][Npad] dL/dkappa_line
     float* gline;                // [3][L] per-line sums (sorted order)
+    float* partial;              // [S+1][n_rchunk] reduction partials
+    int n_rchunk;
 };
+
+static constexpr int RCHUNK = 2048;      // lines per reduction partial
 
 // Kernel launchers (pz_kernels.hip).  Each enqueues on the stream and returns
 // the hipError_t of the launch.
@@ -113,9 +117,18 @@ struct pz_plan {
     float* kappa;
     float* gk;
     float* gline;
+    float* partial;
+    int n_rchunk;
+    float* seed;         // [Npad] loss seed written by the batched chi^2 stage
+    int64_t* tile_cost;  // host [n_tiles]: Voigt evaluations per opacity tile
     void* base;          // single device allocation holding everything above
     // stage profiling (see pz_plan_profile)
     bool prof;
     int prof_n[PZ_N_STAGES];
     hipEvent_t* prof_ev;  // [PZ_N_STAGES][PZ_PROFILE_SLOTS][2], created on first enable
+    // who last wrote kappa / lp (see synth_backward)
+    bool ws_valid;
+    pz_atmos ws_atm;
+    pz_params ws_par;
+    hipStream_t ws_stream;
 };

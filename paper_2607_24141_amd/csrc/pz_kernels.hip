@@ -1,297 +1,27 @@
-// HIP kernels (gfx950) of the synthesis path: populations, per-(line, depth)
-// parameters, the tiled windowed-Voigt opacity accumulation, the depth scan
-// with the formal solution, and the adjoint (reverse scan, line-parallel
-// gather, deterministic reductions).
+// Per-star HIP kernels (gfx950): thin wrappers that map the grid onto the
+// stage bodies of pz_stages.h, plus their launchers.
 #include <hip/hip_runtime.h>
-#include <math.h>
 
-#include "pz_internal.h"
-#include "pz_voigt.h"
+#include "pz_stages.h"
 
 namespace pz {
 
-static constexpr int WAVE = 64;
-
-// ------------------------------------------------------------ populations
-// Two-stage Saha ionisation (Sec. 3, Eq. 11) with no ionisation lowering:
-//   Phi = (2 U_II / U_I) (2 pi m_e k T / h^2)^{3/2} exp(-chi / kT) / n_e,
-//   f_I = 1/(1+Phi), f_II = Phi/(1+Phi); infinite chi => single stage.
-// Output n_{s,r}/(rho U_{s,r}) with the abundance correction 10^dA (Eq. 30).
-__global__ void k_populations(StarDev s) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= s.S * s.D) return;
-    const int sp = idx / s.D, j = idx - sp * s.D;
-    const double T = s.T[j];
-    const double chi = s.chi_ion[sp];
-    const double U0 = s.U[(sp * 2 + 0) * s.D + j];
-    const double U1 = s.U[(sp * 2 + 1) * s.D + j];
-    const double saha = pow(2.0 * PI * M_ELECTRON * K_BOLTZ / (H_PLANCK * H_PLANCK), 1.5);
-    double fI = 1.0, fII = 0.0;
-    if (isfinite(chi)) {
-        const double phi = 2.0 * U1 / U0 * saha * T * sqrt(T) * exp(-chi * EV_ERG / (K_BOLTZ * T)) / s.ne[j];
-        if (phi <= 1.0) {
-            fI = 1.0 / (1.0 + phi);
-            fII = phi * fI;
-        } else {
-            fII = 1.0 / (1.0 + 1.0 / phi);
-            fI = fII / phi;
-        }
-    }
-    const double n = (s.dA ? exp10((double)s.dA[sp]) : 1.0) * s.n_species[sp * s.D + j];
-    s.pop[(sp * 2 + 0) * s.D + j] = n * fI / (s.rho[j] * U0);
-    s.pop[(sp * 2 + 1) * s.D + j] = n * fII / (s.rho[j] * U1);
+__global__ __launch_bounds__(256) void k_populations(StarDev s) {
+    dev_populations(s, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// ------------------------------------------------------ line-depth params
-// Per (line, depth), in float64 then rounded (Eqs. 4-5, 30):
-//   dv = sqrt(2kT/m + xi^2),  dnu_D = dv / lambda_l
-//   a  = 10^ddamp (g_rad + g_S n_e + g_vdW n_pert) / (4 pi dnu_D)
-//   K  = (pi e^2/m_e c) n/(rho U) 10^(loggf+dgf) e^{-E/kT} (1 - e^{-h nu_l/kT}) / (sqrt(pi) dnu_D)
-// stored as (c/dv, a, K, a^2); v = (lambda_l/lambda_i - 1) c/dv.
-__global__ void k_line_params(StarDev s) {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)s.L * s.D) return;
-    const int l = (int)(idx / s.D), j = (int)(idx - (long)l * s.D);
-    const double T = s.T[j];
-    const int spion = s.ln.spion[l];
-    const int sp = spion >> 1;
-    const int caller = s.ln.perm[l];
-    const double xi = (double)s.xi[0] * 1.0e5;
-    const double mass = s.mass[sp] * AMU_G;
-    const double dv = sqrt(2.0 * K_BOLTZ * T / mass + xi * xi);
-    const double lam = s.ln.lam_cm[l];
-    double gam = exp10(s.ln.lgr[l]) + exp10(s.ln.lgs[l]) * s.ne[j] + exp10(s.ln.lgw[l]) * s.npert[j];
-    if (s.ddamp) gam *= exp10((double)s.ddamp[caller]);
-    const double a = gam * lam / (4.0 * PI * dv);
-    const double loggf = s.ln.loggf[l] + (s.dgf ? (double)s.dgf[caller] : 0.0);
-    const double line_const = PI * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT);
-    const double kT = K_BOLTZ * T;
-    const double strength = line_const * s.pop[spion * s.D + j] * exp10(loggf) *
-                            exp(-s.ln.E_eV[l] * EV_ERG / kT) * (-expm1(-H_PLANCK * C_LIGHT / (lam * kT)));
-    const double K = strength * lam / (sqrt(PI) * dv);
-    s.lp[idx] = make_float4((float)(C_LIGHT / dv), (float)a, (float)K, (float)(a * a));
+__global__ __launch_bounds__(256) void k_line_params(StarDev s) {
+    dev_line_params(s, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
-
-// x = lambda_l / lambda_i - 1 = expm1(delta - k h), k = i - ic: the
-// detuning from an integer pixel offset and a float64-derived sub-pixel
-// offset, so no large frequencies are subtracted in float32.
-__device__ __forceinline__ float detuning(int k, float delta, float h_hi, float h_lo) {
-    const float kf = (float)k;
-    const float t = fmaf(-kf, h_lo, fmaf(-kf, h_hi, delta));
-    return t * fmaf(t, fmaf(t, fmaf(t, 1.0f / 24.0f, 1.0f / 6.0f), 0.5f), 1.0f);
-}
-
-// -------------------------------------------------------------- opacity
-// A workgroup of 8 wavefronts owns TPX = 8 WPX consecutive pixels x all
-// depths.  Each wavefront covers WPX pixels x NDG = 64/WPX depth groups, so
-// its lanes see nearby detunings (little divergence between the Voigt
-// regions) and a line's window edge masks few lanes.  Thread (px, dg)
-// accumulates depths j = d NDG + dg of its pixel in registers.  The lines
-// overlapping the tile are a contiguous range of the sorted list; their
-// per-depth parameters are staged through LDS in chunks.  No atomics: every
-// (pixel, depth) sum is owned by one thread and runs in sorted-line order.
-static constexpr int MAX_CHUNK = 16;
-
-struct alignas(16) LineLds {
-    float delta;
-    int ic, ilo, ihi;
-};
 
 template <int WPX>
 __global__ __launch_bounds__(512) void k_opacity(StarDev s, int chunk) {
-    constexpr int NDG = 64 / WPX;
-    constexpr int DPT = (MAXD + NDG - 1) / NDG;
-    constexpr int TPX = 8 * WPX;
     __shared__ float4 s_lp[MAX_CHUNK * MAXD];
     __shared__ LineLds s_ln[MAX_CHUNK];
-    const int tid = threadIdx.x;
-    const int lane = tid % 64;
-    const int px = lane % WPX;
-    const int dg = lane / WPX;
-    const int w0 = blockIdx.x * TPX + (tid / 64) * WPX;   // first pixel of this wavefront
-    const int i = w0 + px;
-    const int D = s.D;
-    const int l0 = s.tile_first[blockIdx.x], l1 = s.tile_last[blockIdx.x];
-    float acc[DPT];
-#pragma unroll
-    for (int d = 0; d < DPT; ++d) acc[d] = 0.0f;
-
-    for (int c0 = l0; c0 < l1; c0 += chunk) {
-        const int nc = min(chunk, l1 - c0);
-        const float4* src = s.lp + (size_t)c0 * D;
-        for (int k = tid; k < nc * D; k += 512) {
-            const int q = k / D;
-            s_lp[q * MAXD + (k - q * D)] = src[k];
-        }
-        if (tid < nc) {
-            LineLds t;
-            t.delta = s.ln.delta[c0 + tid];
-            t.ic = s.ln.ic[c0 + tid];
-            t.ilo = s.ln.ilo[c0 + tid];
-            t.ihi = s.ln.ihi[c0 + tid];
-            s_ln[tid] = t;
-        }
-        __syncthreads();
-        for (int q = 0; q < nc; ++q) {
-            const LineLds ln = s_ln[q];
-            if (i >= ln.ilo && i <= ln.ihi) {
-                const float x = detuning(i - ln.ic, ln.delta, s.h_hi, s.h_lo);
-                const float4* row = s_lp + q * MAXD;
-#pragma unroll
-                for (int d = 0; d < DPT; ++d) {
-                    const int j = d * NDG + dg;
-                    if (j < D) {
-                        const float4 p = row[j];
-                        const float v = x * p.x;
-                        acc[d] = fmaf(p.z, voigt_H(p.y, p.w, v, v * v), acc[d]);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (i < s.N) {
-#pragma unroll
-        for (int d = 0; d < DPT; ++d) {
-            const int j = d * NDG + dg;
-            if (j < D) s.kappa[(size_t)j * s.Npad + i] = acc[d];
-        }
-    }
+    dev_opacity_tile<WPX>(s, blockIdx.x, chunk, s_lp, s_ln);
 }
 
-// ------------------------------------------------------- formal solution
-// Piecewise-linear S(tau) between depths, diffusion lower boundary and a
-// linear extrapolation of S to tau = 0 (Eq. 7), summed from the surface down:
-//   I(0, mu) = C_top + sum_j A_j c_j + A_{D-1} I_D,
-//   A_j = exp(-tau_j / mu),  x_j = (tau_{j+1} - tau_j)/mu,
-//   c_j = S_j (1 - e^{-x_j}) + (S_{j+1} - S_j) lw(x_j),
-//   lw(x) = (1 - (1 + x) e^{-x}) / x,
-//   C_top = S_top (1 - e^{-x_t}) + (S_0 - S_top) lw(x_t), x_t = tau_0/mu,
-//   S_top = S_0 - tau_0 (S_1 - S_0)/(tau_1 - tau_0),
-//   I_D = S_{D-1} + mu (S_{D-1} - S_{D-2}) / (tau_{D-1} - tau_{D-2}).
-// This is the bottom-up recurrence of the formal solution unrolled into a
-// sum, so a single top-down pass with O(1) state per ray suffices.
-// 3-point Gauss-Legendre on [0, 1]: mu = 1/2 -+ sqrt(3/5)/2, 1/2; w = 5/18, 8/18, 5/18
-static constexpr double kMu0 = 0.1127016653792583, kMu1 = 0.5, kMu2 = 0.8872983346207417;
-__constant__ float c_mu[3] = {(float)kMu0, (float)kMu1, (float)kMu2};
-__constant__ float c_inv_mu[3] = {(float)(1.0 / kMu0), (float)(1.0 / kMu1), (float)(1.0 / kMu2)};
-__constant__ float c_wmu[3] = {(float)(2.0 * PI * 5.0 / 18.0 * kMu0), (float)(2.0 * PI * 8.0 / 18.0 * kMu1),
-                               (float)(2.0 * PI * 5.0 / 18.0 * kMu2)};  // 2 pi w_k mu_k
-
-struct ExpTerms {
-    float e, om, lw, dlw;   // e^-x, 1 - e^-x, lw(x), lw'(x)
-};
-
-__device__ __forceinline__ ExpTerms exp_terms(float x, bool need_d) {
-    ExpTerms r;
-    r.e = expf(-x);
-    r.om = -expm1f(-x);
-    if (x < 0.05f) {
-        // series of lw and lw' (sum_{n>=2} (-1)^n (n-1) x^{n-1}/n! and its derivative)
-        r.lw = x * fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 144.0f, -1.0f / 30.0f), 0.125f), -1.0f / 3.0f), 0.5f);
-        r.dlw = need_d ? fmaf(x, fmaf(x, fmaf(x, fmaf(x, 5.0f / 144.0f, -2.0f / 15.0f), 0.375f), -2.0f / 3.0f), 0.5f) : 0.0f;
-    } else {
-        const float inv = 1.0f / x;
-        r.lw = fmaf(-x, r.e, r.om) * inv;
-        r.dlw = need_d ? fmaf(-r.lw, inv, r.e) : 0.0f;
-    }
-    return r;
-}
-
-struct Ray3 {
-    float F[3], A[3];
-    __device__ void top(float S0, float S1, float t0, float t1) {
-        const float S_top = S0 - t0 * (S1 - S0) / (t1 - t0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms et = exp_terms(t0 * c_inv_mu[k], false);
-            F[k] = fmaf(S_top, et.om, (S0 - S_top) * et.lw);
-            A[k] = et.e;
-        }
-    }
-    __device__ void seg(float Sa, float Sb, float ta, float tb) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms et = exp_terms((tb - ta) * c_inv_mu[k], false);
-            const float c = fmaf(Sa, et.om, (Sb - Sa) * et.lw);
-            F[k] = fmaf(A[k], c, F[k]);
-            A[k] *= et.e;
-        }
-    }
-    __device__ float bottom(float Sa, float Sb, float ta, float tb) {
-        const float grad = (Sb - Sa) / (tb - ta);
-        float out = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float ID = fmaf(c_mu[k], grad, Sb);
-            out = fmaf(c_wmu[k], fmaf(A[k], ID, F[k]), out);
-        }
-        return out;
-    }
-};
-
-struct PixelSetup {
-    float kc;        // continuum per unit mass
-    float c1;        // 2 h c^2 / lambda^5 per nm
-    float c2;        // h c / (lambda k)
-};
-
-__device__ __forceinline__ PixelSetup pixel_setup(const StarDev& s, int i) {
-    const double lnl = log(s.lam_first_nm) + (double)i * s.h;
-    const double lam_cm = exp(lnl) * 1.0e-7;
-    PixelSetup p;
-    p.kc = (float)(s.kappa0 * exp(s.alpha * (lnl - log(s.lam_ref_nm))));
-    const double l2 = lam_cm * lam_cm;
-    p.c1 = (float)(2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7);
-    p.c2 = (float)(H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ));
-    return p;
-}
-
-__device__ __forceinline__ float planck(const PixelSetup& p, float invT) {
-    return p.c1 / expm1f(p.c2 * invT);
-}
-
-__global__ __launch_bounds__(256) void k_flux(StarDev s) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.N) return;
-    const PixelSetup p = pixel_setup(s, i);
-    const int D = s.D;
-    const float* kl = s.kappa + i;
-    const size_t st = s.Npad;
-    float m0 = (float)s.m[0];
-    float S0 = planck(p, (float)(1.0 / s.T[0]));
-    float chi_t = p.kc + kl[0];
-    float tt0 = chi_t * m0;
-    float tc0 = p.kc * m0;
-    float m1 = (float)s.m[1];
-    float S1 = planck(p, (float)(1.0 / s.T[1]));
-    float chi_t1 = p.kc + kl[st];
-    float tt1 = fmaf(0.5f * (chi_t + chi_t1), m1 - m0, tt0);
-    float tc1 = fmaf(p.kc, m1 - m0, tc0);
-    Ray3 rt, rc;
-    rt.top(S0, S1, tt0, tt1);
-    rc.top(S0, S1, tc0, tc1);
-    float Sa = S0, Sb = S1, ta = tt0, tb = tt1, ca = tc0, cb = tc1;
-    float chi_b = chi_t1, mb = m1;
-    for (int j = 1; j < D; ++j) {
-        if (j > 1) {
-            const float mj = (float)s.m[j];
-            const float chi_j = p.kc + kl[(size_t)j * st];
-            Sa = Sb;
-            ta = tb;
-            ca = cb;
-            Sb = planck(p, (float)(1.0 / s.T[j]));
-            tb = fmaf(0.5f * (chi_b + chi_j), mj - mb, ta);
-            cb = fmaf(p.kc, mj - mb, ca);
-            chi_b = chi_j;
-            mb = mj;
-        }
-        rt.seg(Sa, Sb, ta, tb);
-        rc.seg(Sa, Sb, ca, cb);
-    }
-    s.F[i] = rt.bottom(Sa, Sb, ta, tb);
-    s.Fc[i] = rc.bottom(Sa, Sb, ca, cb);
-}
+__global__ __launch_bounds__(256) void k_flux(StarDev s) { dev_flux(s, blockIdx.x * blockDim.x + threadIdx.x); }
 
 __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, float* F) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,243 +41,37 @@ __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, f
     F[i] = r.bottom(Sa, Sb, ta, tb);
 }
 
-// ---------------------------------------------------------- reverse scan
-// dL/dkappa_line[j][i] for the seed dL/dF_i (total branch only: the
-// continuum branch depends on no correction).  dF/dtau_k is local in k in the
-// summed form above:
-//   from A_k:           -A_k c_k / mu                        (k <= D-2)
-//   from x_j:           +A_j c'_j / mu to tau_{j+1}, -A_j c'_j / mu to tau_j,
-//                       c'_j = S_j e_j + (S_{j+1} - S_j) lw'(x_j)
-//   bottom:             -A_{D-1} I_D / mu to tau_{D-1};  -/+ A_{D-1} mu dS/dtau^2
-//   top slab:           via x_t and S_top (tau_0 and tau_1)
-// then dL/dchi_j from the trapezoid tau scan by suffix sums Gamma_j.
 template <int MD>
 __global__ __launch_bounds__(64) void k_reverse_scan(StarDev s) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.N) return;
-    const int D = s.D;
-    const float G = s.dLdF[i];
-    float gt[MD];
-#pragma unroll
-    for (int j = 0; j < MD; ++j) gt[j] = 0.0f;
-    const PixelSetup p = pixel_setup(s, i);
-    const float* kl = s.kappa + i;
-    const size_t st = s.Npad;
-    // surface quantities
-    const float m0 = (float)s.m[0], m1 = (float)s.m[1];
-    const float S0 = planck(p, (float)(1.0 / s.T[0]));
-    const float S1 = planck(p, (float)(1.0 / s.T[1]));
-    const float chi0 = p.kc + kl[0], chi1 = p.kc + kl[st];
-    const float t0 = chi0 * m0;
-    const float t1 = fmaf(0.5f * (chi0 + chi1), m1 - m0, t0);
-    const float dt01 = t1 - t0;
-    const float sig = (S1 - S0) / dt01;
-    const float S_top = S0 - t0 * sig;
-    float A[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float Gk = G * c_wmu[k];
-        const ExpTerms et = exp_terms(t0 * c_inv_mu[k], true);
-        const float dCdx = fmaf(S_top, et.e, (S0 - S_top) * et.dlw);
-        const float dCdS = et.om - et.lw;
-        gt[0] += Gk * (dCdx * c_inv_mu[k] + dCdS * (-sig - t0 * sig / dt01));
-        gt[1] += Gk * dCdS * (t0 * sig / dt01);
-        A[k] = et.e;
-    }
-    // segments
-    float Sa = S0, Sb = S1, ta = t0, tb = t1, chib = chi1, mb = m1;
-#pragma unroll
-    for (int j = 0; j < MD - 1; ++j) {
-        if (j + 1 < D) {
-            if (j > 0) {
-                const float mj = (float)s.m[j + 1];
-                const float chij = p.kc + kl[(size_t)(j + 1) * st];
-                Sa = Sb;
-                ta = tb;
-                Sb = planck(p, (float)(1.0 / s.T[j + 1]));
-                tb = fmaf(0.5f * (chib + chij), mj - mb, ta);
-                chib = chij;
-                mb = mj;
-            }
-            float ga = 0.0f, gb = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float Gk = G * c_wmu[k];
-                const ExpTerms et = exp_terms((tb - ta) * c_inv_mu[k], true);
-                const float c = fmaf(Sa, et.om, (Sb - Sa) * et.lw);
-                const float dc = fmaf(Sa, et.e, (Sb - Sa) * et.dlw);
-                const float w = Gk * A[k] * c_inv_mu[k];
-                ga -= w * (c + dc);
-                gb += w * dc;
-                A[k] *= et.e;
-            }
-            gt[j] += ga;
-            gt[j + 1] += gb;
-        }
-    }
-    // bottom boundary (Sa, Sb, ta, tb are now the last segment)
-    {
-        const float dS = Sb - Sa, dtl = tb - ta;
-        float g_last = 0.0f, g_prev = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float Gk = G * c_wmu[k] * A[k];
-            const float ID = fmaf(c_mu[k], dS / dtl, Sb);
-            const float q = c_mu[k] * dS / (dtl * dtl);
-            g_last += Gk * (-ID * c_inv_mu[k] - q);
-            g_prev += Gk * q;
-        }
-#pragma unroll
-        for (int j = 0; j < MD; ++j) {
-            if (j == D - 1) gt[j] += g_last;
-            if (j == D - 2) gt[j] += g_prev;
-        }
-    }
-    // dL/dchi_j from the trapezoid rule via suffix sums
-    float suffix = 0.0f, gnext = 0.0f;
-    float* out = s.gk + i;
-#pragma unroll
-    for (int j = MD - 1; j >= 0; --j) {
-        if (j < D) {
-            suffix += gt[j];
-            float g;
-            if (j == D - 1) {
-                g = 0.0f;
-            } else {
-                g = 0.5f * (float)(s.m[j + 1] - s.m[j]) * gnext;
-            }
-            if (j == 0) g += (float)s.m[0] * suffix;
-            else g += 0.5f * (float)(s.m[j] - s.m[j - 1]) * suffix;
-            out[(size_t)j * st] = g;
-            gnext = suffix;
-        }
-    }
-}
-
-// -------------------------------------------------------- gather (adjoint)
-// One wavefront per line: its lanes are 8 pixels x 8 depth groups and step
-// through the window 8 pixels at a time; the line's per-depth parameters stay
-// in registers.  The Voigt function and its derivatives are recomputed:
-//   dL/d dgf   = ln10 sum g K H
-//   dL/d ddamp = ln10 sum g K a dH/da
-//   dL/d xi    = sum g (-K) (H + a dH/da + v dH/dv) d ln dnu_D / d xi,
-//   d ln dnu_D / d xi = xi / dv^2 = xi (s / c)^2 with s = c/dv  (per km/s: x 1e10)
-// A fixed-order butterfly reduces across lanes, so the sums are deterministic.
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
-    return x;
+    dev_reverse_scan<MD>(s, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_gather(StarDev s) {
-    constexpr int WPX = 8, NDG = 8, DPT = (MAXD + NDG - 1) / NDG;
-    const int lane = threadIdx.x % WAVE;
     const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / WAVE) + (int)(threadIdx.x / WAVE));
-    if (l >= s.L) return;
-    const int px = lane % WPX, dg = lane / WPX;
-    const int ilo = s.ln.ilo[l], ihi = s.ln.ihi[l], ic = s.ln.ic[l];
-    const float delta = s.ln.delta[l];
-    const int D = s.D;
-    const float4* lp = s.lp + (size_t)l * D;
-    const float xi_f = s.xi[0] * (float)(1.0e10 / (C_LIGHT * C_LIGHT));
-    float sgf = 0.0f, sd = 0.0f, sxi = 0.0f;
-    for (int p0 = ilo; p0 <= ihi; p0 += WPX) {
-        const int i = p0 + px;
-        if (i <= ihi) {
-            const float x = detuning(i - ic, delta, s.h_hi, s.h_lo);
-            const float* g = s.gk + i;
-#pragma unroll 1
-            for (int d = 0; d < DPT; ++d) {
-                const int j = d * NDG + dg;
-                if (j < D) {
-                    const float4 q = lp[j];
-                    const float gK = g[(size_t)j * s.Npad] * q.z;
-                    const float v = x * q.x;
-                    float H, aHa, X;
-                    voigt_HD(q.y, q.w, v, v * v, H, aHa, X);
-                    sgf = fmaf(gK, H, sgf);
-                    sd = fmaf(gK, aHa, sd);
-                    sxi = fmaf(-gK * X, xi_f * q.x * q.x, sxi);
-                }
-            }
-        }
-    }
-    sgf = wave_sum(sgf);
-    sd = wave_sum(sd);
-    sxi = wave_sum(sxi);
-    if (lane == 0) {
-        s.gline[l] = (float)LN10 * sgf;
-        s.gline[s.L + l] = (float)LN10 * sd;
-        s.gline[2 * s.L + l] = sxi;
-    }
+    dev_gather(s, l, threadIdx.x % WAVE);
 }
 
-// ----------------------------------------------------------- reductions
-__global__ void k_scatter_lines(StarDev s) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= s.L) return;
-    const int c = s.ln.perm[l];
-    if (s.g_loggf) s.g_loggf[c] = s.gline[l];
-    if (s.g_damp) s.g_damp[c] = s.gline[s.L + l];
-}
+__global__ __launch_bounds__(256) void k_scatter_lines(StarDev s) { dev_scatter(s, blockIdx.x * blockDim.x + threadIdx.x); }
 
-// Block b < S: abundance gradient of species b = sum of the dgf gradients of
-// its lines (10^dA and 10^dgf scale the same strength at fixed atmosphere).
-// Block S: microturbulence = sum of the per-line terms.  Fixed-order sums.
-__global__ __launch_bounds__(256) void k_reduce_species_xi(StarDev s) {
+__global__ __launch_bounds__(256) void k_reduce_partials(StarDev s) {
     __shared__ float red[256];
-    const int b = blockIdx.x;
-    float acc = 0.0f;
-    if (b < s.S) {
-        const int o0 = s.sp_off[b], o1 = s.sp_off[b + 1];
-        for (int k = o0 + threadIdx.x; k < o1; k += 256) acc += s.gline[s.sp_idx[k]];
-    } else {
-        for (int k = threadIdx.x; k < s.L; k += 256) acc += s.gline[2 * s.L + k];
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (b < s.S) {
-            if (s.g_abund) s.g_abund[b] = red[0];
-        } else if (s.g_xi) {
-            s.g_xi[0] = red[0];
-        }
-    }
+    dev_reduce_partial(s, blockIdx.x, blockIdx.y, red);
 }
 
-// ------------------------------------------------------------- loss seed
-// f = F/Fc, r = 2 (f - y)/sigma^2: dL/dF = r/Fc, dL/dFc = -r F/Fc^2.
-__global__ void k_chi2_seed(int N, const float* F, const float* Fc, const float* y, float inv_s2, float* gF,
-                            float* gFc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const float inv_c = 1.0f / Fc[i];
-    const float f = F[i] * inv_c;
-    const float r = 2.0f * (f - y[i]) * inv_s2;
-    gF[i] = r * inv_c;
-    if (gFc) gFc[i] = -r * f * inv_c;
+__global__ __launch_bounds__(256) void k_reduce_final(StarDev s) {
+    __shared__ float red[256];
+    dev_reduce_final(s, blockIdx.x, red);
 }
 
-// Single-block fixed-order sum of ((f - y)/sigma)^2.
+__global__ __launch_bounds__(256) void k_chi2_seed(int N, const float* F, const float* Fc, const float* y, float inv_s2,
+                                                   float* gF, float* gFc) {
+    dev_chi2_seed(N, F, Fc, y, inv_s2, gF, gFc, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __global__ __launch_bounds__(1024) void k_chi2_loss(int N, const float* F, const float* Fc, const float* y,
                                                     float inv_s2, float* loss) {
     __shared__ float red[1024];
-    float acc = 0.0f;
-    for (int i = threadIdx.x; i < N; i += 1024) {
-        const float d = F[i] / Fc[i] - y[i];
-        acc = fmaf(d * d, inv_s2, acc);
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss[0] = red[0];
+    dev_chi2_loss(N, F, Fc, y, inv_s2, loss, red);
 }
 
 // ------------------------------------------------------------- launchers
@@ -593,7 +117,8 @@ hipError_t launch_gather(const StarDev& s, hipStream_t st) {
 
 hipError_t launch_reduce(const StarDev& s, hipStream_t st) {
     if (s.L > 0) k_scatter_lines<<<(s.L + 255) / 256, 256, 0, st>>>(s);
-    k_reduce_species_xi<<<s.S + 1, 256, 0, st>>>(s);
+    k_reduce_partials<<<dim3(s.n_rchunk, s.S + 1), 256, 0, st>>>(s);
+    k_reduce_final<<<s.S + 1, 256, 0, st>>>(s);
     return hipGetLastError();
 }
 
