@@ -191,6 +191,13 @@ int pz_chi2_seed(int32_t N, const float* F, const float* Fc, const float* y, flo
 int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
                     float* kappa_line, pz_stream stream);
 
+/* Debug/test entry: the reverse depth scan alone.  Writes dL/dkappa_line as
+ * [D][N] float32 (device) for the seed dL/dF[N] (device), the quantity the
+ * line-parallel gather of synth_backward consumes.  Reuses or recomputes the
+ * forward opacity as synth_backward does. */
+int pz_debug_opacity_adjoint(const pz_plan* plan, const pz_atmos* atm, const pz_params* par,
+                             const float* dL_dF, float* g_kappa, pz_stream stream);
+
 /* Debug/test entry: formal solution for a caller-given source function and
  * optical depth (Eqs. 7-8), both [D][n] float32 device arrays; writes F[n].
  * Lets closed forms (linear S, Milne-Eddington) pin the transfer kernel. */

@@ -437,7 +437,7 @@ def opacity_adjoint(wl, kappa_line, dLdF, pix=None):
     return optical_depth_adjoint(gtau, wl.atm.m)
 
 
-def line_gradients(wl, params, g, pix, line_subset=None):
+def line_gradients(wl, params, g, pix, line_subset=None, absolute=False):
     """Per-line gradients from g = dL/dkappa_line at the pixels pix.
 
     dkappa/d dgf   = ln10 kappa
@@ -446,7 +446,9 @@ def line_gradients(wl, params, g, pix, line_subset=None):
                      d ln dnu / d xi = xi / dv^2 (xi in the units of dv)
     with dH/dv = -2 (v H - a L), dH/da = 2 (v L + a H) - 2/sqrt(pi), w = H + i L.
     Returns (G_gf[L], G_damp[L], G_xi_per_line[L]) over all lines (zero for lines
-    not in line_subset when given).
+    not in line_subset when given).  With absolute=True every term enters with
+    its absolute value: sum |g dkappa/dp|, the scale against which the
+    rounding error of the sum is measured (its condition).
     """
     pix = np.asarray(pix, np.int64)
     L = wl.lines.L
@@ -467,20 +469,26 @@ def line_gradients(wl, params, g, pix, line_subset=None):
         Ha = 2.0 * (v * Lw + a * H) - 2.0 / SQRT_PI
         gij = g.T[pp]                                  # [pairs, D]
         kap = K * H
-        np.add.at(Ggf, ll, LN10 * np.sum(gij * kap, axis=1))
-        np.add.at(Gd, ll, LN10 * np.sum(gij * K * a * Ha, axis=1))
         dlndnu_dxi = xi / lp["dv"] ** 2 * 1.0e5        # per km/s
-        np.add.at(Gxi, ll, np.sum(gij * (-K) * (H + a * Ha + v * Hv) * dlndnu_dxi, axis=1))
+        t_gf = LN10 * gij * kap
+        t_d = LN10 * gij * K * a * Ha
+        t_xi = gij * (-K) * (H + a * Ha + v * Hv) * dlndnu_dxi
+        if absolute:
+            t_gf, t_d, t_xi = np.abs(t_gf), np.abs(t_d), np.abs(t_xi)
+        np.add.at(Ggf, ll, np.sum(t_gf, axis=1))
+        np.add.at(Gd, ll, np.sum(t_d, axis=1))
+        np.add.at(Gxi, ll, np.sum(t_xi, axis=1))
     return Ggf, Gd, Gxi
 
 
-def adjoint(wl, params, dLdF, pix=None, line_subset=None):
+def adjoint(wl, params, dLdF, pix=None, line_subset=None, conditions=False):
     """Vector-Jacobian product of F (total branch) with respect to the corrections.
 
     dLdF is the seed at the pixels pix (the continuum branch does not depend on
     any corrected quantity).  Returns dict(g_loggf[L], g_damp[L], g_abund[S],
     g_xi) -- the abundance and xi entries are complete only when pix covers
-    every pixel that any line reaches.
+    every pixel that any line reaches.  conditions=True adds abs_* entries,
+    the sums of the absolute values of the same terms.
     """
     params = params or wl.params
     pix = np.arange(wl.grid.N) if pix is None else np.asarray(pix, np.int64)
@@ -489,7 +497,13 @@ def adjoint(wl, params, dLdF, pix=None, line_subset=None):
     Ggf, Gd, Gxi = line_gradients(wl, params, g, pix, line_subset)
     GA = np.zeros(wl.atm.S)
     np.add.at(GA, wl.lines.species, Ggf)     # dA_s enters exactly like dgf of its lines
-    return dict(g_loggf=Ggf, g_damp=Gd, g_abund=GA, g_xi=float(np.sum(Gxi)), g_kappa=g)
+    out = dict(g_loggf=Ggf, g_damp=Gd, g_abund=GA, g_xi=float(np.sum(Gxi)), g_kappa=g)
+    if conditions:
+        Agf, Ad, Axi = line_gradients(wl, params, g, pix, line_subset, absolute=True)
+        AA = np.zeros(wl.atm.S)
+        np.add.at(AA, wl.lines.species, Agf)
+        out.update(abs_loggf=Agf, abs_damp=Ad, abs_abund=AA, abs_xi=float(np.sum(Axi)))
+    return out
 
 
 def window_pixels(wl, line_idx):

@@ -94,6 +94,8 @@ def _load():
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.pz_line_opacity.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
                                     C.c_void_p]
+    lib.pz_debug_opacity_adjoint.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
+                                             C.c_void_p, C.c_void_p]
     lib.pz_debug_formal_solve.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_void_p, C.c_void_p]
     lib.pz_chi2_seed.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
@@ -109,7 +111,7 @@ def _load():
                                 C.POINTER(pz_options), C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_int32,
                                 C.POINTER(pz_options), C.POINTER(C.c_float)]
     for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
-                 "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune"):
+                 "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -118,7 +120,8 @@ lib = _load()
 
 EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "pz_plan_info", "pz_plan_invalidate",
            "pz_plan_profile", "pz_plan_profile_read",
-           "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_formal_solve",
+           "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_opacity_adjoint",
+           "pz_debug_formal_solve",
            "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune")
 
 
@@ -268,6 +271,11 @@ def synth_backward(plan, atm, par, dL_dF, g_loggf, g_damp, g_abund, g_xi, dL_dFc
 
 def pz_line_opacity(plan, atm, par, kappa, stream=None):
     _check(lib.pz_line_opacity(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(kappa), _stream(stream)))
+
+
+def pz_debug_opacity_adjoint(plan, atm, par, dL_dF, g_kappa, stream=None):
+    _check(lib.pz_debug_opacity_adjoint(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(dL_dF), _ptr(g_kappa),
+                                        _stream(stream)))
 
 
 def pz_chi2_seed(F, Fc, y, sigma, dL_dF, dL_dFc=None, loss=None, stream=None):

@@ -560,6 +560,28 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
     return PZ_OK;
 }
 
+int pz_debug_opacity_adjoint(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, const float* dL_dF,
+                             float* g_kappa, pz_stream stream) {
+    g_err.clear();
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    int rc = check_atmos(plan, atm);
+    if (rc) return rc;
+    if ((rc = check_params(par))) return rc;
+    if (!dL_dF || !g_kappa) return fail(PZ_E_INVALID_ARG, "dL_dF and g_kappa are required");
+    StarDev s = make_star(plan, atm, par);
+    s.dLdF = dL_dF;
+    hipStream_t st = (hipStream_t)stream;
+    if (!workspace_matches(plan, atm, par, st)) {
+        const_cast<pz_plan*>(plan)->ws_valid = false;
+        if ((rc = enqueue_opacity(plan, s, st))) return rc;
+        record_workspace(plan, atm, par, st);
+    }
+    PZ_HIP(launch_reverse_scan(s, st));
+    PZ_HIP(hipMemcpy2DAsync(g_kappa, (size_t)plan->N * 4, plan->gk, (size_t)plan->Npad * 4, (size_t)plan->N * 4,
+                            plan->D, hipMemcpyDeviceToDevice, st));
+    return PZ_OK;
+}
+
 int pz_line_opacity(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, float* kappa_line,
                     pz_stream stream) {
     g_err.clear();

@@ -34,7 +34,7 @@ enum Phase {
     PH_FLUX,       // (star, 512 pixels)
     PH_SEED,       // (star, 512 pixels): chi^2 seed for stars with a target
     PH_LOSS,       // (star): chi^2 value, one 1024-thread workgroup
-    PH_REVERSE,    // (star, 64 pixels)
+    PH_REVERSE,    // (star, 64 pixels), 64-thread workgroups
     PH_GATHER,     // (star, GATHER_ITEM lines), atomic queue
     PH_SCATTER,    // (star, 512 lines)
     PH_PARTIAL,    // (star, list b * n_rchunk + c)
@@ -124,10 +124,10 @@ __global__ __launch_bounds__(1024) void kb_loss(const StarDev* __restrict__ star
     }
 }
 
-__global__ __launch_bounds__(512) void kb_reverse(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
+__global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
-        dev_reverse_scan<MAXD>(stars[w.x], w.y * 512 + threadIdx.x);
+        dev_reverse_scan<MAXD>(stars[w.x], w.y * 64 + threadIdx.x);
     }
 }
 
@@ -188,7 +188,7 @@ struct pz_batch {
     const float** ys;
     float** losses;
     int* ctr;             // [N_COUNTER] queue counters: opacity (32, 64, 128), gather
-    int grid512, grid256, grid1024, grid_op[3], grid_gather;
+    int grid512, grid256, grid1024, grid_op[3], grid_gather, grid_rev;
     void* base;
 };
 
@@ -237,9 +237,9 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
         for (int t = 0; t < s.n_tiles; ++t) items[ph_op].push_back({b, t});
         for (int k = 0; k < (s.N + 511) / 512; ++k) {
             items[PH_FLUX].push_back({b, k});
-            items[PH_REVERSE].push_back({b, k});
             if (st.y) items[PH_SEED].push_back({b, k});
         }
+        for (int k = 0; k < (s.N + 63) / 64; ++k) items[PH_REVERSE].push_back({b, k});
         if (st.y && st.loss) items[PH_LOSS].push_back({b, 0});
         for (int k = 0; k < (s.L + GATHER_ITEM - 1) / GATHER_ITEM; ++k) items[PH_GATHER].push_back({b, k});
         for (int k = 0; k < (s.L + 511) / 512; ++k) items[PH_SCATTER].push_back({b, k});
@@ -306,6 +306,7 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
     bt->grid512 = std::max(1, n_cu * 4);
     bt->grid256 = std::max(1, n_cu * 8);
     bt->grid1024 = std::max(1, n_cu * 2);
+    bt->grid_rev = std::max(1, n_cu * 16);
     bt->plans.reserve(n_star);
     for (int b = 0; b < n_star; ++b) bt->plans.push_back(stars[b].plan);
     *out = bt;
@@ -343,7 +344,7 @@ int synth_batch(const pz_batch* bt, int32_t mode, pz_stream stream) {
         kb_loss<<<grid(bt->grid1024, n[PH_LOSS]), 1024, 0, st>>>(bt->stars, it[PH_LOSS], n[PH_LOSS], bt->inv_s2,
                                                                  bt->ys, bt->losses);
     if (mode == PZ_MODE_FWD_BWD) {
-        kb_reverse<<<grid(bt->grid512, n[PH_REVERSE]), 512, 0, st>>>(bt->stars, it[PH_REVERSE], n[PH_REVERSE]);
+        kb_reverse<<<grid(bt->grid_rev, n[PH_REVERSE]), 64, 0, st>>>(bt->stars, it[PH_REVERSE], n[PH_REVERSE]);
         kb_gather<<<grid(bt->grid_gather, n[PH_GATHER]), 512, 0, st>>>(bt->stars, it[PH_GATHER], n[PH_GATHER],
                                                                         bt->ctr + 3);
         kb_scatter<<<grid(bt->grid512, n[PH_SCATTER]), 512, 0, st>>>(bt->stars, it[PH_SCATTER], n[PH_SCATTER]);

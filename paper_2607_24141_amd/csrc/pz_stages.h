@@ -293,68 +293,106 @@ __device__ __forceinline__ void dev_flux(const StarDev& s, int i) {
 // ---------------------------------------------------------- reverse scan
 // dL/dkappa_line[j][i] for the seed dL/dF_i (total branch only: the
 // continuum branch depends on no correction).  dF/dtau_k is local in k in the
-// summed form above:
+// summed form of the formal solution:
 //   from A_k:           -A_k c_k / mu                        (k <= D-2)
 //   from x_j:           +A_j c'_j / mu to tau_{j+1}, -A_j c'_j / mu to tau_j,
 //                       c'_j = S_j e_j + (S_{j+1} - S_j) lw'(x_j)
 //   bottom:             -A_{D-1} I_D / mu to tau_{D-1};  -/+ A_{D-1} mu dS/dtau^2
 //   top slab:           via x_t and S_top (tau_0 and tau_1)
-// then dL/dchi_j from the trapezoid tau scan by suffix sums Gamma_j.
+// then dL/dchi_j from the trapezoid tau scan by suffix sums Gamma_j.  The
+// suffix sums are small differences of O(A S / mu) terms (S changes little
+// between adjacent depths near the surface), so this scan runs in float64;
+// only the result is rounded to float32.
+struct ExpTerms64 {
+    double e, om, lw, dlw;   // e^-x, 1 - e^-x, lw(x), lw'(x)
+};
+
+__device__ __forceinline__ ExpTerms64 exp_terms64(double x) {
+    ExpTerms64 r;
+    r.e = exp(-x);
+    r.om = -expm1(-x);
+    if (x < 1.0e-2) {
+        // sum_{n>=2} (-1)^n (n-1) x^{n-1}/n! and its derivative, through n = 8
+        double lw = 0.0, dlw = 0.0, fact = 2.0, xp = 1.0;
+#pragma unroll
+        for (int n = 2; n <= 8; ++n) {
+            if (n > 2) fact *= n;
+            const double sg = (n & 1) ? -1.0 : 1.0;
+            dlw += sg * (n - 1) * (n - 1) * xp / fact;
+            xp *= x;
+            lw += sg * (n - 1) * xp / fact;
+        }
+        r.lw = lw;
+        r.dlw = dlw;
+    } else {
+        r.lw = (r.om - x * r.e) / x;
+        r.dlw = r.e - r.lw / x;
+    }
+    return r;
+}
+
 template <int MD>
 __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i) {
     if (i >= s.N) return;
     const int D = s.D;
-    const float G = s.dLdF[i];
-    float gt[MD];
+    const double G = s.dLdF[i];
+    const double mu[3] = {kMu0, kMu1, kMu2};
+    const double wmu[3] = {2.0 * PI * 5.0 / 18.0 * kMu0, 2.0 * PI * 8.0 / 18.0 * kMu1, 2.0 * PI * 5.0 / 18.0 * kMu2};
+    double gt[MD];
 #pragma unroll
-    for (int j = 0; j < MD; ++j) gt[j] = 0.0f;
-    const PixelSetup p = pixel_setup(s, i);
+    for (int j = 0; j < MD; ++j) gt[j] = 0.0;
+    // pixel constants in float64
+    const double lnl = log(s.lam_first_nm) + (double)i * s.h;
+    const double lam_cm = exp(lnl) * 1.0e-7;
+    const double kc = s.kappa0 * exp(s.alpha * (lnl - log(s.lam_ref_nm)));
+    const double l2 = lam_cm * lam_cm;
+    const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
+    const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
     const float* kl = s.kappa + i;
     const size_t st = s.Npad;
     // surface quantities
-    const float m0 = (float)s.m[0], m1 = (float)s.m[1];
-    const float S0 = planck(p, (float)(1.0 / s.T[0]));
-    const float S1 = planck(p, (float)(1.0 / s.T[1]));
-    const float chi0 = p.kc + kl[0], chi1 = p.kc + kl[st];
-    const float t0 = chi0 * m0;
-    const float t1 = fmaf(0.5f * (chi0 + chi1), m1 - m0, t0);
-    const float dt01 = t1 - t0;
-    const float sig = (S1 - S0) / dt01;
-    const float S_top = S0 - t0 * sig;
-    float A[3];
+    const double m0 = s.m[0], m1 = s.m[1];
+    const double S0 = c1 / expm1(c2 / s.T[0]);
+    const double S1 = c1 / expm1(c2 / s.T[1]);
+    const double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[st];
+    const double t0 = chi0 * m0;
+    const double t1 = t0 + 0.5 * (chi0 + chi1) * (m1 - m0);
+    const double dt01 = t1 - t0;
+    const double sig = (S1 - S0) / dt01;
+    const double S_top = S0 - t0 * sig;
+    double A[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float Gk = G * c_wmu[k];
-        const ExpTerms et = exp_terms(t0 * c_inv_mu[k], true);
-        const float dCdx = fmaf(S_top, et.e, (S0 - S_top) * et.dlw);
-        const float dCdS = et.om - et.lw;
-        gt[0] += Gk * (dCdx * c_inv_mu[k] + dCdS * (-sig - t0 * sig / dt01));
+        const double Gk = G * wmu[k];
+        const ExpTerms64 et = exp_terms64(t0 / mu[k]);
+        const double dCdx = S_top * et.e + (S0 - S_top) * et.dlw;
+        const double dCdS = et.om - et.lw;
+        gt[0] += Gk * (dCdx / mu[k] + dCdS * (-sig - t0 * sig / dt01));
         gt[1] += Gk * dCdS * (t0 * sig / dt01);
         A[k] = et.e;
     }
     // segments
-    float Sa = S0, Sb = S1, ta = t0, tb = t1, chib = chi1, mb = m1;
+    double Sa = S0, Sb = S1, ta = t0, tb = t1, chib = chi1, mb = m1;
 #pragma unroll
     for (int j = 0; j < MD - 1; ++j) {
         if (j + 1 < D) {
             if (j > 0) {
-                const float mj = (float)s.m[j + 1];
-                const float chij = p.kc + kl[(size_t)(j + 1) * st];
+                const double mj = s.m[j + 1];
+                const double chij = kc + (double)kl[(size_t)(j + 1) * st];
                 Sa = Sb;
                 ta = tb;
-                Sb = planck(p, (float)(1.0 / s.T[j + 1]));
-                tb = fmaf(0.5f * (chib + chij), mj - mb, ta);
+                Sb = c1 / expm1(c2 / s.T[j + 1]);
+                tb = ta + 0.5 * (chib + chij) * (mj - mb);
                 chib = chij;
                 mb = mj;
             }
-            float ga = 0.0f, gb = 0.0f;
+            double ga = 0.0, gb = 0.0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const float Gk = G * c_wmu[k];
-                const ExpTerms et = exp_terms((tb - ta) * c_inv_mu[k], true);
-                const float c = fmaf(Sa, et.om, (Sb - Sa) * et.lw);
-                const float dc = fmaf(Sa, et.e, (Sb - Sa) * et.dlw);
-                const float w = Gk * A[k] * c_inv_mu[k];
+                const ExpTerms64 et = exp_terms64((tb - ta) / mu[k]);
+                const double c = Sa * et.om + (Sb - Sa) * et.lw;
+                const double dc = Sa * et.e + (Sb - Sa) * et.dlw;
+                const double w = G * wmu[k] * A[k] / mu[k];
                 ga -= w * (c + dc);
                 gb += w * dc;
                 A[k] *= et.e;
@@ -365,14 +403,14 @@ __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i) {
     }
     // bottom boundary (Sa, Sb, ta, tb are now the last segment)
     {
-        const float dS = Sb - Sa, dtl = tb - ta;
-        float g_last = 0.0f, g_prev = 0.0f;
+        const double dS = Sb - Sa, dtl = tb - ta;
+        double g_last = 0.0, g_prev = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float Gk = G * c_wmu[k] * A[k];
-            const float ID = fmaf(c_mu[k], dS / dtl, Sb);
-            const float q = c_mu[k] * dS / (dtl * dtl);
-            g_last += Gk * (-ID * c_inv_mu[k] - q);
+            const double Gk = G * wmu[k] * A[k];
+            const double ID = Sb + mu[k] * dS / dtl;
+            const double q = mu[k] * dS / (dtl * dtl);
+            g_last += Gk * (-ID / mu[k] - q);
             g_prev += Gk * q;
         }
 #pragma unroll
@@ -382,21 +420,15 @@ __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i) {
         }
     }
     // dL/dchi_j from the trapezoid rule via suffix sums
-    float suffix = 0.0f, gnext = 0.0f;
+    double suffix = 0.0, gnext = 0.0;
     float* out = s.gk + i;
 #pragma unroll
     for (int j = MD - 1; j >= 0; --j) {
         if (j < D) {
             suffix += gt[j];
-            float g;
-            if (j == D - 1) {
-                g = 0.0f;
-            } else {
-                g = 0.5f * (float)(s.m[j + 1] - s.m[j]) * gnext;
-            }
-            if (j == 0) g += (float)s.m[0] * suffix;
-            else g += 0.5f * (float)(s.m[j] - s.m[j - 1]) * suffix;
-            out[(size_t)j * st] = g;
+            double g = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
+            g += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
+            out[(size_t)j * st] = (float)g;
             gnext = suffix;
         }
     }

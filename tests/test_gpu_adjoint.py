@@ -1,10 +1,14 @@
 """GPU vector-Jacobian product (Sec. 6, Eq. 30 corrections) against the FP64
 oracle adjoint with the identical seed, through the C ABI.
 
-Gradient tolerance (1e-3 relative): an entry passes iff
-|g - g_ref| <= 1e-3 |g_ref| where |g_ref| >= 1e-2 max|g_ref|, and
-|g - g_ref| <= 1e-5 max|g_ref| for the smaller entries (near-zero gradients
-carry no relative precision in float32).
+Gradient tolerance.  A gradient is a sum over (pixel, depth) terms
+t = dL/dkappa dkappa/dp that can cancel heavily (random-sign seeds, or the
+noise-dominated residuals of a chi^2 fit).  Each float32 term carries a
+relative error of order 1e-6 (Voigt evaluation <= 1.5e-6, float32 rounding of
+the per-(line, depth) parameters and of dL/dkappa), so the achievable error
+is |g - g_ref| <= 1e-3 |g_ref| + 1e-5 sum|t|: 1e-3 relative for every
+gradient whose terms cancel by less than a factor 100, and an error bounded by
+the term accuracy otherwise.  sum|t| comes from the oracle (conditions=True).
 """
 import numpy as np
 import pytest
@@ -14,6 +18,20 @@ import workloads as W
 from oracle import synth as O
 
 pytestmark = pytest.mark.gpu
+
+
+TERM_TOL = 1e-5
+
+
+def grad_close_cond(got, ref, abs_sum, rtol=1e-3, name=""):
+    """|g - g_ref| <= rtol |g_ref| + TERM_TOL sum|t|; returns the share within rtol alone."""
+    got, ref, a = (np.atleast_1d(np.asarray(x, np.float64)) for x in (got, ref, abs_sum))
+    err = np.abs(got - ref)
+    bound = rtol * np.abs(ref) + TERM_TOL * a
+    bad = np.flatnonzero(err > bound)
+    assert bad.size == 0, (name, bad[:5], got[bad[:5]], ref[bad[:5]], a[bad[:5]])
+    nz = np.abs(ref) > 0
+    return float(np.mean(err[nz] <= rtol * np.abs(ref[nz]))) if nz.any() else 1.0
 
 
 def grad_close(got, ref, rtol=1e-3, name=""):
@@ -51,12 +69,12 @@ def test_vjp_tiny_vs_oracle(gpu_lib, seed, L, N, D, xi):
     wl.params = W.random_params(rng, L, 4, xi)
     s = rng.normal(size=N).astype(np.float32)
     g = gpu_vjp(gpu_lib, wl, s)
-    ref = O.adjoint(wl, wl.params, s.astype(np.float64))
-    grad_close(g[0], ref["g_loggf"], name="loggf")
-    grad_close(g[1], ref["g_damp"], name="damp")
-    grad_close(g[2], ref["g_abund"], name="abund")
+    ref = O.adjoint(wl, wl.params, s.astype(np.float64), conditions=True)
+    grad_close_cond(g[0], ref["g_loggf"], ref["abs_loggf"], name="loggf")
+    grad_close_cond(g[1], ref["g_damp"], ref["abs_damp"], name="damp")
+    grad_close_cond(g[2], ref["g_abund"], ref["abs_abund"], name="abund")
     if xi > 0:
-        grad_close(g[3], [ref["g_xi"]], name="xi")
+        grad_close_cond(g[3], ref["g_xi"], ref["abs_xi"], name="xi")
     else:
         assert abs(g[3][0]) <= 1e-5 * np.max(np.abs(ref["g_loggf"])) + 1e-30
 
@@ -115,3 +133,75 @@ def test_autograd_function(gpu_lib):
     g = gpu_vjp(gpu_lib, wl, w.cpu().numpy(), plan)
     np.testing.assert_array_equal(dgf.grad.cpu().numpy(), g[0])
     np.testing.assert_array_equal(xi.grad.cpu().numpy(), g[3])
+
+
+@pytest.mark.parametrize("seed,L,N,D", [(51, 30, 600, 72), (52, 8, 300, 8)])
+def test_reverse_scan_vs_oracle(gpu_lib, seed, L, N, D):
+    """dL/dkappa_line of the reverse depth scan, elementwise, against the oracle's
+    reverse of the formal solution and tau scan (per pixel, relative to the
+    largest |dL/dkappa| over depth)."""
+    pz = gpu_lib
+    wl = W.tiny(seed=seed, L=L, N=N, D=D)
+    rng = np.random.default_rng(seed)
+    s = rng.normal(size=N).astype(np.float32)
+    plan = pz.plan_for(wl)
+    g = torch.empty((D, N), device="cuda")
+    pz.pz_debug_opacity_adjoint(plan, pz.Atmos(wl.atm), pz.Params.from_host(wl.params),
+                                torch.as_tensor(s, device="cuda"), g)
+    torch.cuda.synchronize()
+    kl = O.line_opacity(wl)
+    ref = O.opacity_adjoint(wl, kl, s.astype(np.float64))
+    err = np.abs(g.cpu().numpy() - ref) / np.max(np.abs(ref), axis=0, keepdims=True)
+    print("max rel err of dL/dkappa", err.max())
+    assert err.max() <= 2e-5
+
+
+def test_reverse_scan_1500_1700nm_sampled(gpu_lib):
+    pz = gpu_lib
+    wl = W.config2()
+    rng = np.random.default_rng(3)
+    s = rng.normal(size=wl.grid.N).astype(np.float32)
+    plan = pz.plan_for(wl)
+    g = torch.empty((plan.D, plan.N), device="cuda")
+    pz.pz_debug_opacity_adjoint(plan, pz.Atmos(wl.atm), pz.Params.from_host(wl.params),
+                                torch.as_tensor(s, device="cuda"), g)
+    torch.cuda.synchronize()
+    pix = np.unique(rng.integers(0, wl.grid.N, 48))
+    kl = O.line_opacity(wl, pix=pix)
+    ref = O.opacity_adjoint(wl, kl, s[pix].astype(np.float64), pix)
+    err = np.abs(g.cpu().numpy()[:, pix] - ref) / np.max(np.abs(ref), axis=0, keepdims=True)
+    print("max rel err of dL/dkappa", err.max())
+    assert err.max() <= 2e-5
+
+
+def test_backward_reuses_only_matching_forward(gpu_lib):
+    """synth_backward reuses the forward opacity only for the same descriptors and
+    stream; other inputs (or pz_plan_invalidate) force a recompute: results equal
+    a fresh backward bitwise in every case."""
+    pz = gpu_lib
+    wl = W.tiny(seed=61, L=50, N=900, D=72)
+    plan = pz.plan_for(wl)
+    atm = pz.Atmos(wl.atm)
+    pa = pz.Params.from_host(W.random_params(np.random.default_rng(1), plan.L, plan.S, 1.0))
+    pb = pz.Params.from_host(W.random_params(np.random.default_rng(2), plan.L, plan.S, 1.5))
+    F = torch.empty(plan.N, device="cuda")
+    Fc = torch.empty_like(F)
+    s = torch.as_tensor(np.random.default_rng(3).normal(size=plan.N).astype(np.float32), device="cuda")
+
+    def bwd(par):
+        g = [torch.empty(plan.L, device="cuda"), torch.empty(plan.L, device="cuda"),
+             torch.empty(plan.S, device="cuda"), torch.empty(1, device="cuda")]
+        pz.synth_backward(plan, atm, par, s, *g)
+        torch.cuda.synchronize()
+        return [x.cpu().numpy() for x in g]
+
+    plan.invalidate()
+    fresh_b = bwd(pb)
+    plan.invalidate()
+    fresh_a = bwd(pa)
+    pz.synth_forward(plan, atm, pa, F, Fc)
+    reused_a = bwd(pa)                 # same descriptors: reuses the forward opacity
+    pz.synth_forward(plan, atm, pa, F, Fc)
+    other_b = bwd(pb)                  # different corrections: recomputes
+    for x, y in zip(reused_a + other_b, fresh_a + fresh_b):
+        np.testing.assert_array_equal(x, y)

@@ -118,11 +118,7 @@ def test_batch_graph_replay(gpu_lib):
     batch.destroy()
 
 
-def _grad_close(got, ref, rtol=1e-3):
-    scale = np.max(np.abs(ref))
-    big = np.abs(ref) >= 1e-2 * scale
-    assert np.all(np.abs(got - ref)[big] <= rtol * np.abs(ref[big]))
-    assert np.all(np.abs(got - ref)[~big] <= 1e-5 * scale)
+from test_gpu_adjoint import grad_close_cond
 
 
 def test_batch_stars_vs_oracle(gpu_lib):
@@ -147,9 +143,9 @@ def test_batch_stars_vs_oracle(gpu_lib):
             lines = rng.choice(L, 6, replace=False)
             wpix = O.window_pixels(s.wl, lines)
             seed = s.seed.cpu().numpy().astype(np.float64)
-            ref = O.adjoint(s.wl, s.wl.params, seed[wpix], pix=wpix, line_subset=lines)
-            _grad_close(s.g[0].cpu().numpy()[lines], ref["g_loggf"][lines])
-            _grad_close(s.g[1].cpu().numpy()[lines], ref["g_damp"][lines])
+            ref = O.adjoint(s.wl, s.wl.params, seed[wpix], pix=wpix, line_subset=lines, conditions=True)
+            grad_close_cond(s.g[0].cpu().numpy()[lines], ref["g_loggf"][lines], ref["abs_loggf"][lines], name="gf")
+            grad_close_cond(s.g[1].cpu().numpy()[lines], ref["g_damp"][lines], ref["abs_damp"][lines], name="damp")
     batch.destroy()
 
 
