@@ -29,8 +29,10 @@ METRIC = "spectra/s, Voigt evals/s: fwd, fwd+bwd, batched vs plain fwd at 1e-4 r
 # rcp, FMA = 8), a * sum (1), kappa += K H (2).
 FLOPS_PER_EVAL = 34
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
-KERNEL_SOURCES = ("paper_2607_24141_amd/csrc/pz_kernels.hip", "paper_2607_24141_amd/csrc/pz_voigt.h",
-                  "paper_2607_24141_amd/csrc/voigt_consts.h")
+# sources of the opacity kernel: a committed HBM-traffic measurement is used only if they are unchanged
+KERNEL_SOURCES = ("paper_2607_24141_amd/csrc/pz_kernels.hip", "paper_2607_24141_amd/csrc/pz_stages.h",
+                  "paper_2607_24141_amd/csrc/pz_voigt.h", "paper_2607_24141_amd/csrc/voigt_consts.h",
+                  "paper_2607_24141_amd/csrc/pz_internal.h")
 
 
 def log(*a):
@@ -102,6 +104,8 @@ def main():
     ap.add_argument("--modes", default="fwd,fwdbwd,batch")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -238,6 +242,15 @@ def main():
         batch.destroy()
         for p in plans:
             p.destroy()
+
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

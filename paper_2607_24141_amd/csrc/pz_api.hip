@@ -214,6 +214,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     const int n_rchunk = (int)((Ls + RCHUNK - 1) / RCHUNK);
     const size_t o_part = take((size_t)(S + 1) * n_rchunk * 4);
     const size_t o_seed = take((size_t)Npad * 4);
+    const size_t o_order = take((size_t)n_tiles * 4), o_qctr = take(4);
     // Voigt evaluations per tile (orders the batched opacity work)
     std::vector<int64_t> tcost(n_tiles, 0);
     for (int k = 0; k < L; ++k) {
@@ -280,6 +281,12 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->partial = (float*)(base + o_part);
     p->n_rchunk = n_rchunk;
     p->seed = (float*)(base + o_seed);
+    p->tile_order = (int*)(base + o_order);
+    p->qctr = (int*)(base + o_qctr);
+    std::vector<int> torder(n_tiles);
+    std::iota(torder.begin(), torder.end(), 0);
+    std::stable_sort(torder.begin(), torder.end(), [&](int a, int b) { return tcost[a] > tcost[b]; });
+    p->grid_opacity = opacity_grid(tile_px);
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
@@ -299,6 +306,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     if (ue == hipSuccess) ue = up(p->tile_first, tfirst.data(), (size_t)n_tiles * 4);
     if (ue == hipSuccess) ue = up(p->tile_last, tlast.data(), (size_t)n_tiles * 4);
     if (ue == hipSuccess) ue = up(p->sp_off, sp_off.data(), (size_t)(S + 1) * 4);
+    if (ue == hipSuccess) ue = up(p->tile_order, torder.data(), (size_t)n_tiles * 4);
     // workspaces start defined (pixels beyond N in the padded rows stay zero)
     if (ue == hipSuccess) ue = hipMemset(p->kappa, 0, (size_t)D * Npad * 4);
     if (ue == hipSuccess) ue = hipMemset(p->gk, 0, (size_t)D * Npad * 4);
@@ -452,6 +460,9 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.gline = p->gline;
     s.partial = p->partial;
     s.n_rchunk = p->n_rchunk;
+    s.tile_order = p->tile_order;
+    s.qctr = p->qctr;
+    s.grid_opacity = p->grid_opacity;
     return s;
 }
 

@@ -81,12 +81,16 @@ struct StarDev {
     float* gline;                // [3][L] per-line sums (sorted order)
     float* partial;              // [S+1][n_rchunk] reduction partials
     int n_rchunk;
+    const int* tile_order;       // opacity work queue (decreasing cost)
+    int* qctr;
+    int grid_opacity;
 };
 
 static constexpr int RCHUNK = 2048;      // lines per reduction partial
 
 // Kernel launchers (pz_kernels.hip).  Each enqueues on the stream and returns
 // the hipError_t of the launch.
+int opacity_grid(int tile_px);   // persistent opacity workgroups for this device
 hipError_t launch_populations(const StarDev& s, hipStream_t st);
 hipError_t launch_line_params(const StarDev& s, hipStream_t st);
 hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st);
@@ -120,6 +124,9 @@ struct pz_plan {
     float* partial;
     int n_rchunk;
     float* seed;         // [Npad] loss seed written by the batched chi^2 stage
+    int* tile_order;     // [n_tiles] tiles by decreasing cost (opacity work queue)
+    int* qctr;           // [1] opacity work-queue counter
+    int grid_opacity;    // persistent opacity workgroups (CUs x occupancy)
     int64_t* tile_cost;  // host [n_tiles]: Voigt evaluations per opacity tile
     void* base;          // single device allocation holding everything above
     // stage profiling (see pz_plan_profile)

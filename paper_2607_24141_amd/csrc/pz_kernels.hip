@@ -2,6 +2,8 @@
 // stage bodies of pz_stages.h, plus their launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pz_stages.h"
 
 namespace pz {
@@ -14,11 +16,39 @@ __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
     dev_line_params(s, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Persistent workgroups take tiles from a queue ordered by decreasing cost
+// (longest-processing-time first): tiles differ several-fold in line count
+// (band clusters), and a one-shot grid of ~N/TPX workgroups leaves a long
+// tail of heavy tiles.
 template <int WPX>
 __global__ __launch_bounds__(512) void k_opacity(StarDev s, int chunk) {
     __shared__ float4 s_lp[MAX_CHUNK * MAXD];
     __shared__ LineLds s_ln[MAX_CHUNK];
-    dev_opacity_tile<WPX>(s, blockIdx.x, chunk, s_lp, s_ln);
+    __shared__ int s_it;
+    for (;;) {
+        if (threadIdx.x == 0) s_it = atomicAdd(s.qctr, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_it);
+        __syncthreads();
+        if (it >= s.n_tiles) return;
+        dev_opacity_tile<WPX>(s, s.tile_order[it], chunk, s_lp, s_ln);
+    }
+}
+
+__global__ void k_reset_queue(int* ctr) { ctr[0] = 0; }
+
+int opacity_grid(int tile_px) {
+    int dev = 0, n_cu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1024;
+    hipError_t e = hipSuccess;
+    switch (tile_px) {
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_opacity<4>, 512, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_opacity<8>, 512, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_opacity<16>, 512, 0); break;
+    }
+    if (e != hipSuccess || occ < 1) occ = 1;
+    return n_cu * occ;
 }
 
 __global__ __launch_bounds__(256) void k_flux(StarDev s) { dev_flux(s, blockIdx.x * blockDim.x + threadIdx.x); }
@@ -90,10 +120,12 @@ hipError_t launch_line_params(const StarDev& s, hipStream_t st) {
 
 hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
     if (s.n_tiles == 0) return hipSuccess;
+    const int grid = std::max(1, std::min(s.grid_opacity, s.n_tiles));
+    k_reset_queue<<<1, 1, 0, st>>>(s.qctr);
     switch (s.tile_px) {
-        case 32: k_opacity<4><<<s.n_tiles, 512, 0, st>>>(s, chunk); break;
-        case 64: k_opacity<8><<<s.n_tiles, 512, 0, st>>>(s, chunk); break;
-        case 128: k_opacity<16><<<s.n_tiles, 512, 0, st>>>(s, chunk); break;
+        case 32: k_opacity<4><<<grid, 512, 0, st>>>(s, chunk); break;
+        case 64: k_opacity<8><<<grid, 512, 0, st>>>(s, chunk); break;
+        case 128: k_opacity<16><<<grid, 512, 0, st>>>(s, chunk); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
