@@ -123,9 +123,9 @@ def main():
     dev = "cuda"
     log("generating 1500-1700 nm workload")
     wl = W.config4()
-    plan = pz.plan_for(wl)
     atm = pz.Atmos(wl.atm)
     par = pz.Params.from_host(wl.params)
+    plan = pz.plan_tuned(wl, atm, par)
     N, L, S = plan.N, plan.L, plan.S
     F = torch.empty(N, dtype=torch.float32, device=dev)
     Fc = torch.empty_like(F)
@@ -157,7 +157,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name.replace("_fwdbwd", ""), "lambda_nm": [1500, 1700], "R": 3.0e5,
                    "N": N, "D": plan.D, "L": L, "S": S, "window_nm": wl.window_nm, "quadrature": "gauss3",
-                   "mode": "fwd", "tile_px": plan.tile_px},
+                   "mode": "fwd", "tile_px": plan.tile_px, "autotune_key": pz.tune_key(wl)},
         "voigt_evals_per_s": plan.voigt_evals / (ms_fwd * 1e-3),
         "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
         "roofline": {"bound": "alu", "kernel": "k_opacity", "achieved": achieved_tflops,
@@ -203,7 +203,14 @@ def main():
         from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(16) as ex:
             stars_wl = list(ex.map(W.batch_star, range(nb)))
-            plans = list(ex.map(lambda w: pz.plan_for(w), stars_wl))
+        opts = {}
+        for w in stars_wl:                      # one autotune per size bucket
+            k = pz.tune_key(w)
+            if k not in opts:
+                opts[k] = pz.tuned_options(w)
+        with ThreadPoolExecutor(16) as ex:
+            plans = list(ex.map(lambda w: pz.plan_for(w, tile_px=opts[pz.tune_key(w)][0],
+                                                      lines_per_chunk=opts[pz.tune_key(w)][1]), stars_wl))
         keep, descr, total_evals = [], [], 0
         rng = np.random.default_rng(5)
         for w, p in zip(stars_wl, plans):
@@ -236,7 +243,7 @@ def main():
                           "fwd_bwd_spectra_per_s": nb * 1000.0 / ms_bb, "fwd_bwd_ms": ms_bb,
                           "fwd_voigt_evals_per_s": total_evals / (ms_bf * 1e-3),
                           "fwd_bwd_over_fwd": ms_bb / ms_bf,
-                          "evals_per_fwd": total_evals,
+                          "evals_per_fwd": total_evals, "tile_px_used": sorted(set(p.tile_px for p in plans)),
                           "pixels": int(sum(p.N for p in plans)), "lines": int(sum(p.L for p in plans))}
         del graphs
         batch.destroy()

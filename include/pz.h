@@ -95,7 +95,7 @@ typedef struct {
 /* Plan options. Zero fields take defaults. */
 typedef struct {
     double window_nm;           /* W: line l reaches pixel i iff |lambda_i - lambda_l| <= W (> 0) */
-    int32_t quadrature;         /* PZ_QUAD_GAUSS3 (default) or PZ_QUAD_E2             */
+    int32_t quadrature;         /* PZ_QUAD_GAUSS3 (default, FP32) or PZ_QUAD_E2 (FP64) */
     int32_t tile_px;            /* opacity tile width in pixels: 0 = autotuned/default */
     int32_t lines_per_chunk;    /* lines staged in LDS per step: 0 = default          */
     int32_t flags;              /* reserved, must be 0                                 */
@@ -200,6 +200,7 @@ int pz_debug_opacity_adjoint(const pz_plan* plan, const pz_atmos* atm, const pz_
 
 /* Debug/test entry: formal solution for a caller-given source function and
  * optical depth (Eqs. 7-8), both [D][n] float32 device arrays; writes F[n].
+ * quadrature is PZ_QUAD_GAUSS3 or PZ_QUAD_E2 (anything else: PZ_E_INVALID).
  * Lets closed forms (linear S, Milne-Eddington) pin the transfer kernel. */
 int pz_debug_formal_solve(int32_t D, int32_t n, const float* S, const float* tau,
                           int32_t quadrature, float* F, pz_stream stream);

@@ -228,6 +228,49 @@ def plan_for(workload, **kw):
                 quadrature=PZ_QUAD_GAUSS3 if workload.quadrature == "gauss3" else PZ_QUAD_E2, **kw)
 
 
+# --------------------------------------------------------------- autotuning
+TUNE_CACHE = os.path.join(_HERE, "autotune_cache.json")
+
+
+def tune_key(workload):
+    """Size bucket of a workload: GPU arch, log2 of pixels, log2 of lines per pixel window, depths."""
+    import math
+    import torch
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    N, L = workload.grid.N, workload.lines.L
+    win_px = 2.0 * workload.window_nm / (workload.grid.lam_first_nm / workload.grid.R)
+    overlap = max(L * win_px / N, 1.0)
+    return "%s|N%d|ov%d|D%d" % (arch, int(math.log2(N)), int(math.log2(overlap)), workload.atm.D)
+
+
+def tuned_options(workload, atm=None, par=None, reps=3, cache_path=TUNE_CACHE):
+    """(tile_px, lines_per_chunk) for a workload: from the cache, else pz_autotune (then cached)."""
+    import json
+    key = tune_key(workload)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        return tuple(cache[key][:2])
+    atm = atm or Atmos(workload.atm)
+    par = par or Params.from_host(workload.params)
+    tile, chunk, ms = pz_autotune(workload.grid, workload.lines, workload.atm.S, workload.atm.D, atm, par,
+                                  window_nm=workload.window_nm, reps=reps)
+    cache[key] = [tile, chunk, ms]
+    if cache_path:
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return tile, chunk
+
+
+def plan_tuned(workload, atm=None, par=None, **kw):
+    tile, chunk = tuned_options(workload, atm, par, **kw)
+    return plan_for(workload, tile_px=tile, lines_per_chunk=chunk)
+
+
 # ----------------------------------------------------------------- atmosphere
 class Atmos:
     """Device copy (float64) of an atmosphere and its pz_atmos descriptor."""

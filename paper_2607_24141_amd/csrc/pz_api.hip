@@ -114,8 +114,6 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
         return fail(PZ_E_INVALID_ARG, "window_nm must be finite and > 0");
     if (opts->quadrature != PZ_QUAD_GAUSS3 && opts->quadrature != PZ_QUAD_E2)
         return fail(PZ_E_INVALID_ARG, "unknown quadrature %d", opts->quadrature);
-    if (opts->quadrature == PZ_QUAD_E2)
-        return fail(PZ_E_UNSUPPORTED, "E2 quadrature is not implemented on the GPU path");
     int tile_px = opts->tile_px ? opts->tile_px : 64;
     if (tile_px != 32 && tile_px != 64 && tile_px != 128)
         return fail(PZ_E_INVALID_ARG, "tile_px must be 0, 32, 64 or 128 (got %d)", opts->tile_px);
@@ -428,6 +426,7 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.tile_px = p->tile_px;
     s.n_tiles = p->n_tiles;
     s.chunk = p->chunk;
+    s.quad = p->quadrature;
     s.lam_first_nm = p->lam_first_nm;
     s.h = p->h;
     s.h_hi = (float)p->h;
@@ -627,10 +626,10 @@ int pz_debug_formal_solve(int32_t D, int32_t n, const float* S, const float* tau
     if (D < 2 || D > PZ_MAX_DEPTH) return fail(PZ_E_SHAPE, "D must be in [2, %d]", PZ_MAX_DEPTH);
     if (n < 0) return fail(PZ_E_SHAPE, "n must be >= 0");
     if (!S || !tau || !F) return fail(PZ_E_INVALID_ARG, "S, tau and F are required");
-    if (quadrature == PZ_QUAD_E2) return fail(PZ_E_UNSUPPORTED, "E2 quadrature is not implemented on the GPU path");
-    if (quadrature != PZ_QUAD_GAUSS3) return fail(PZ_E_INVALID_ARG, "unknown quadrature %d", quadrature);
+    if (quadrature != PZ_QUAD_GAUSS3 && quadrature != PZ_QUAD_E2)
+        return fail(PZ_E_INVALID_ARG, "unknown quadrature %d", quadrature);
     if (n == 0) return PZ_OK;
-    PZ_HIP(launch_debug_formal(D, n, S, tau, F, (hipStream_t)stream));
+    PZ_HIP(launch_debug_formal(D, n, S, tau, quadrature, F, (hipStream_t)stream));
     return PZ_OK;
 }
 

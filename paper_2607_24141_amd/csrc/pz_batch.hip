@@ -99,7 +99,11 @@ __global__ __launch_bounds__(512) void kb_opacity(const StarDev* __restrict__ st
 __global__ __launch_bounds__(512) void kb_flux(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
-        dev_flux(stars[w.x], w.y * 512 + threadIdx.x);
+        const StarDev& s = stars[w.x];
+        if (s.quad == PZ_QUAD_E2)
+            dev_flux_e2(s, w.y * 512 + threadIdx.x);
+        else
+            dev_flux(s, w.y * 512 + threadIdx.x);
     }
 }
 
@@ -127,7 +131,11 @@ __global__ __launch_bounds__(1024) void kb_loss(const StarDev* __restrict__ star
 __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
-        dev_reverse_scan<MAXD>(stars[w.x], w.y * 64 + threadIdx.x);
+        const StarDev& s = stars[w.x];
+        if (s.quad == PZ_QUAD_E2)
+            dev_reverse_scan_e2<MAXD>(s, w.y * 64 + threadIdx.x);
+        else
+            dev_reverse_scan<MAXD>(s, w.y * 64 + threadIdx.x);
     }
 }
 

@@ -41,7 +41,7 @@ struct LineArrays {
 // outputs + workspaces).  Passed by value or stored in the batch table.
 struct StarDev {
     // grid
-    int N, Npad, L, S, D, tile_px, n_tiles, chunk;
+    int N, Npad, L, S, D, tile_px, n_tiles, chunk, quad;
     double lam_first_nm, h;      // h = ln(1 + 1/R)
     float h_hi, h_lo;            // h split for float32 offsets
     LineArrays ln;
@@ -100,7 +100,7 @@ hipError_t launch_gather(const StarDev& s, hipStream_t st);
 hipError_t launch_reduce(const StarDev& s, hipStream_t st);
 hipError_t launch_chi2_seed(int N, const float* F, const float* Fc, const float* y, float sigma, float* gF,
                             float* gFc, float* loss, hipStream_t st);
-hipError_t launch_debug_formal(int D, int n, const float* S, const float* tau, float* F,
+hipError_t launch_debug_formal(int D, int n, const float* S, const float* tau, int quad, float* F,
                                hipStream_t st);
 
 }  // namespace pz

@@ -53,9 +53,29 @@ int opacity_grid(int tile_px) {
 
 __global__ __launch_bounds__(256) void k_flux(StarDev s) { dev_flux(s, blockIdx.x * blockDim.x + threadIdx.x); }
 
-__global__ void k_debug_formal(int D, int n, const float* S, const float* tau, float* F) {
+__global__ __launch_bounds__(64) void k_flux_e2(StarDev s) { dev_flux_e2(s, blockIdx.x * blockDim.x + threadIdx.x); }
+
+__global__ void k_debug_formal(int D, int n, const float* S, const float* tau, int quad, float* F) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (quad == PZ_QUAD_E2) {
+        RayE2 r;
+        r.start();
+        const double S0 = S[i], S1 = S[n + i], t0 = tau[i], t1 = tau[n + i];
+        r.seg(S0 - t0 * (S1 - S0) / (t1 - t0), S0, 0.0, t0);
+        double Sa = S0, Sb = S1, ta = t0, tb = t1;
+        for (int j = 1; j < D; ++j) {
+            if (j > 1) {
+                Sa = Sb;
+                ta = tb;
+                Sb = S[(size_t)j * n + i];
+                tb = tau[(size_t)j * n + i];
+            }
+            r.seg(Sa, Sb, ta, tb);
+        }
+        F[i] = (float)r.bottom(Sa, Sb, ta, tb);
+        return;
+    }
     Ray3 r;
     r.top(S[i], S[n + i], tau[i], tau[n + i]);
     float Sa = S[i], Sb = S[n + i], ta = tau[i], tb = tau[n + i];
@@ -74,6 +94,11 @@ __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, f
 template <int MD>
 __global__ __launch_bounds__(64) void k_reverse_scan(StarDev s) {
     dev_reverse_scan<MD>(s, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int MD>
+__global__ __launch_bounds__(64) void k_reverse_scan_e2(StarDev s) {
+    dev_reverse_scan_e2<MD>(s, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_gather(StarDev s) {
@@ -132,12 +157,18 @@ hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
 }
 
 hipError_t launch_flux(const StarDev& s, hipStream_t st) {
-    k_flux<<<(s.N + 255) / 256, 256, 0, st>>>(s);
+    if (s.quad == PZ_QUAD_E2)
+        k_flux_e2<<<(s.N + 63) / 64, 64, 0, st>>>(s);
+    else
+        k_flux<<<(s.N + 255) / 256, 256, 0, st>>>(s);
     return hipGetLastError();
 }
 
 hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st) {
-    k_reverse_scan<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
+    if (s.quad == PZ_QUAD_E2)
+        k_reverse_scan_e2<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
+    else
+        k_reverse_scan<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
     return hipGetLastError();
 }
 
@@ -162,8 +193,8 @@ hipError_t launch_chi2_seed(int N, const float* F, const float* Fc, const float*
     return hipGetLastError();
 }
 
-hipError_t launch_debug_formal(int D, int n, const float* S, const float* tau, float* F, hipStream_t st) {
-    k_debug_formal<<<(n + 255) / 256, 256, 0, st>>>(D, n, S, tau, F);
+hipError_t launch_debug_formal(int D, int n, const float* S, const float* tau, int quad, float* F, hipStream_t st) {
+    k_debug_formal<<<(n + 255) / 256, 256, 0, st>>>(D, n, S, tau, quad, F);
     return hipGetLastError();
 }
 

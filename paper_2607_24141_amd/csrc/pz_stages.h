@@ -290,6 +290,199 @@ __device__ __forceinline__ void dev_flux(const StarDev& s, int i) {
     s.Fc[i] = rc.bottom(Sa, Sb, ca, cb);
 }
 
+// ------------------------------------------------------------ E2 quadrature
+// Exponential integrals E_n(x), n = 2..4, x >= 0, in float64:
+//   x <= 1: power series E_n(x) = (-x)^{n-1}/(n-1)! (psi(n) - ln x)
+//                                 - sum_{k != n-1} (-x)^k / ((k - n + 1) k!),
+//           psi(n) = -gamma + sum_{m<n} 1/m;
+//   x > 1:  continued fraction E_n(x) = e^{-x} / (x + n - 1 n/(x + n + 2 - 2 (n+1)/(x + n + 4 - ...)))
+//           evaluated with the modified Lentz method.
+// Both loops have fixed upper bounds.
+__device__ __forceinline__ double expint_n(int n, double x) {
+    if (x <= 0.0) return 1.0 / (n - 1);
+    if (x > 700.0) return 0.0;
+    if (x <= 1.0) {
+        const double euler = 0.57721566490153286061;
+        double psi = -euler;
+        for (int m = 1; m < n; ++m) psi += 1.0 / m;
+        double term = 1.0;                       // (-x)^k / k!
+        double sum = (n == 1) ? 0.0 : -1.0 / (1.0 - n);   // k = 0
+        double lead = 0.0;
+        for (int k = 1; k < 60; ++k) {
+            term *= -x / k;
+            if (k == n - 1) {
+                lead = term * (psi - log(x));
+            } else {
+                const double t = term / (k - n + 1);
+                sum -= t;
+                if (k > n && fabs(t) < 1e-18 * fabs(sum)) break;
+            }
+        }
+        return lead + sum;
+    }
+    const double tiny = 1e-300;
+    double b = x + n, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 400; ++i) {
+        const double an = -(double)i * (n - 1 + i);
+        b += 2.0;
+        d = 1.0 / (an * d + b);
+        c = b + an / c;
+        const double del = c * d;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return h * exp(-x);
+}
+
+// F = 2 pi int_0^inf S E2 dt for piecewise-linear S(tau): segment [ta, tb]
+// with S = Sa + s (t - ta) adds Sa (E3(ta) - E3(tb)) + s (E4(ta) - E4(tb) - (tb - ta) E3(tb));
+// below the last depth S continues linearly: S_D E3(tau_D) + s_D E4(tau_D);
+// above the first depth the top slab runs from tau = 0 with the first slope.
+struct RayE2 {
+    double F, E3a, E4a;
+    __device__ void start() {
+        F = 0.0;
+        E3a = 0.5;            // E3(0)
+        E4a = 1.0 / 3.0;      // E4(0)
+    }
+    __device__ void seg(double Sa, double Sb, double ta, double tb) {
+        const double E3b = expint_n(3, tb), E4b = expint_n(4, tb);
+        const double sl = (Sb - Sa) / (tb - ta);
+        F += Sa * (E3a - E3b) + sl * (E4a - E4b - (tb - ta) * E3b);
+        E3a = E3b;
+        E4a = E4b;
+    }
+    __device__ double bottom(double Sa, double Sb, double ta, double tb) const {
+        const double sD = (Sb - Sa) / (tb - ta);
+        return 2.0 * PI * (F + Sb * E3a + sD * E4a);
+    }
+};
+
+__device__ __forceinline__ void dev_flux_e2(const StarDev& s, int i) {
+    if (i >= s.N) return;
+    const double lnl = log(s.lam_first_nm) + (double)i * s.h;
+    const double lam_cm = exp(lnl) * 1.0e-7;
+    const double kc = s.kappa0 * exp(s.alpha * (lnl - log(s.lam_ref_nm)));
+    const double l2 = lam_cm * lam_cm;
+    const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
+    const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
+    const float* kl = s.kappa + i;
+    const size_t st = s.Npad;
+    const int D = s.D;
+    double S0 = c1 / expm1(c2 / s.T[0]), S1 = c1 / expm1(c2 / s.T[1]);
+    double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[st];
+    double t0 = chi0 * s.m[0], t1 = t0 + 0.5 * (chi0 + chi1) * (s.m[1] - s.m[0]);
+    double c0 = kc * s.m[0], cc1 = c0 + kc * (s.m[1] - s.m[0]);
+    RayE2 rt, rc;
+    rt.start();
+    rc.start();
+    // top slab: S_top at tau = 0 from the first segment's slope
+    rt.seg(S0 - t0 * (S1 - S0) / (t1 - t0), S0, 0.0, t0);
+    rc.seg(S0 - c0 * (S1 - S0) / (cc1 - c0), S0, 0.0, c0);
+    double Sa = S0, Sb = S1, ta = t0, tb = t1, ca = c0, cb = cc1, chib = chi1, mb = s.m[1];
+    for (int j = 1; j < D; ++j) {
+        if (j > 1) {
+            const double mj = s.m[j];
+            const double chij = kc + (double)kl[(size_t)j * st];
+            Sa = Sb;
+            ta = tb;
+            ca = cb;
+            Sb = c1 / expm1(c2 / s.T[j]);
+            tb = ta + 0.5 * (chib + chij) * (mj - mb);
+            cb = ca + kc * (mj - mb);
+            chib = chij;
+            mb = mj;
+        }
+        rt.seg(Sa, Sb, ta, tb);
+        rc.seg(Sa, Sb, ca, cb);
+    }
+    s.F[i] = (float)rt.bottom(Sa, Sb, ta, tb);
+    s.Fc[i] = (float)rc.bottom(Sa, Sb, ca, cb);
+}
+
+// Reverse of the E2 flux for the total branch.  With knots t_{-1} = 0,
+// t_k = tau_k and slope s_k of segment k, the E2 terms of adjacent segments
+// cancel at every knot (S is continuous), leaving
+//   segment k >= 1:  dF/dtau_k     += -P_k s_k / dtau_k
+//                    dF/dtau_{k-1} += s_k (E3(tau_k) - E3(tau_{k-1})) + P_k s_k / dtau_k,
+//                    P_k = E4(t_{k-1}) - E4(t_k) - dtau_k E3(t_k);
+//   top slab:        through E3(0) - E3(tau_0), P_0 and the extrapolated S_top;
+//   bottom:          dF/dtau_{D-1} += -s_D E3 - E4 s_D/dtau, dF/dtau_{D-2} += E4 s_D/dtau;
+// all times 2 pi; then the trapezoid suffix sums as for Gauss-3.
+template <int MD>
+__device__ __forceinline__ void dev_reverse_scan_e2(const StarDev& s, int i) {
+    if (i >= s.N) return;
+    const int D = s.D;
+    const double G = 2.0 * PI * (double)s.dLdF[i];
+    double gt[MD];
+#pragma unroll
+    for (int j = 0; j < MD; ++j) gt[j] = 0.0;
+    const double lnl = log(s.lam_first_nm) + (double)i * s.h;
+    const double lam_cm = exp(lnl) * 1.0e-7;
+    const double kc = s.kappa0 * exp(s.alpha * (lnl - log(s.lam_ref_nm)));
+    const double l2 = lam_cm * lam_cm;
+    const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
+    const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
+    const float* kl = s.kappa + i;
+    const size_t st = s.Npad;
+    const double S0 = c1 / expm1(c2 / s.T[0]), S1 = c1 / expm1(c2 / s.T[1]);
+    const double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[st];
+    const double t0 = chi0 * s.m[0];
+    const double t1 = t0 + 0.5 * (chi0 + chi1) * (s.m[1] - s.m[0]);
+    const double d01 = t1 - t0, sig = (S1 - S0) / d01;
+    double E3a = expint_n(3, t0), E4a = expint_n(4, t0);
+    {
+        const double dE3 = 0.5 - E3a;                       // E3(0) - E3(tau_0)
+        const double P0 = 1.0 / 3.0 - E4a - t0 * E3a;        // E4(0) - E4(tau_0) - tau_0 E3(tau_0)
+        gt[0] += G * (dE3 * (-sig - t0 * sig / d01) + P0 * sig / d01);
+        gt[1] += G * (dE3 * (t0 * sig / d01) - P0 * sig / d01);
+    }
+    double Sa = S0, Sb = S1, ta = t0, tb = t1, chib = chi1, mb = s.m[1];
+#pragma unroll
+    for (int j = 0; j < MD - 1; ++j) {
+        if (j + 1 < D) {
+            if (j > 0) {
+                const double mj = s.m[j + 1];
+                const double chij = kc + (double)kl[(size_t)(j + 1) * st];
+                Sa = Sb;
+                ta = tb;
+                Sb = c1 / expm1(c2 / s.T[j + 1]);
+                tb = ta + 0.5 * (chib + chij) * (mj - mb);
+                chib = chij;
+                mb = mj;
+            }
+            const double E3b = expint_n(3, tb), E4b = expint_n(4, tb);
+            const double dt = tb - ta, sl = (Sb - Sa) / dt;
+            const double P = E4a - E4b - dt * E3b;
+            gt[j + 1] += G * (-P * sl / dt);
+            gt[j] += G * (sl * (E3b - E3a) + P * sl / dt);
+            E3a = E3b;
+            E4a = E4b;
+        }
+    }
+    {
+        const double dt = tb - ta, sD = (Sb - Sa) / dt;
+        double g_last = G * (-sD * E3a - E4a * sD / dt), g_prev = G * (E4a * sD / dt);
+#pragma unroll
+        for (int j = 0; j < MD; ++j) {
+            if (j == D - 1) gt[j] += g_last;
+            if (j == D - 2) gt[j] += g_prev;
+        }
+    }
+    double suffix = 0.0, gnext = 0.0;
+    float* out = s.gk + i;
+#pragma unroll
+    for (int j = MD - 1; j >= 0; --j) {
+        if (j < D) {
+            suffix += gt[j];
+            double g = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
+            g += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
+            out[(size_t)j * st] = (float)g;
+            gnext = suffix;
+        }
+    }
+}
+
 // ---------------------------------------------------------- reverse scan
 // dL/dkappa_line[j][i] for the seed dL/dF_i (total branch only: the
 // continuum branch depends on no correction).  dF/dtau_k is local in k in the

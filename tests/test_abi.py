@@ -61,7 +61,7 @@ def _create(pz, grid=None, lines=None, S=2, D=8, opts=None):
 
 @pytest.mark.parametrize("case,code", [
     ("N", -2), ("R", -1), ("lam", -1), ("D", -2), ("Dbig", -2), ("S", -2), ("W", -1), ("quad", -1),
-    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5), ("e2", -6)])
+    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5)])
 def test_plan_validation(pz, case, code):
     import numpy as np
     kw = {}
@@ -91,8 +91,6 @@ def test_plan_validation(pz, case, code):
         kw["lines"] = _lines(pz, ion=np.array([0, 2, 0], np.int32))
     elif case == "nan":
         kw["lines"] = _lines(pz, loggf=np.array([0.0, np.nan, 0.0]))
-    elif case == "e2":
-        kw["opts"] = pz.pz_options(0.3, 1, 0, 0, 0)
     rc, msg = _create(pz, **kw)
     assert rc == code, (rc, msg)
     assert msg

@@ -62,9 +62,11 @@ def gpu_vjp(pz, wl, seed, plan=None):
     return [x.cpu().numpy().astype(np.float64) for x in g]
 
 
-@pytest.mark.parametrize("seed,L,N,D,xi", [(21, 10, 350, 10, 1.4), (22, 60, 900, 72, 0.0), (23, 35, 513, 8, 2.5)])
-def test_vjp_tiny_vs_oracle(gpu_lib, seed, L, N, D, xi):
+@pytest.mark.parametrize("seed,L,N,D,xi,quad", [(21, 10, 350, 10, 1.4, "gauss3"), (22, 60, 900, 72, 0.0, "gauss3"),
+                                                (23, 35, 513, 8, 2.5, "gauss3"), (24, 40, 700, 72, 1.2, "e2")])
+def test_vjp_tiny_vs_oracle(gpu_lib, seed, L, N, D, xi, quad):
     wl = W.tiny(seed=seed, L=L, N=N, D=D, S=4, n_molecular=1, xi=xi)
+    wl.quadrature = quad
     rng = np.random.default_rng(seed)
     wl.params = W.random_params(rng, L, 4, xi)
     s = rng.normal(size=N).astype(np.float32)
@@ -135,13 +137,15 @@ def test_autograd_function(gpu_lib):
     np.testing.assert_array_equal(xi.grad.cpu().numpy(), g[3])
 
 
-@pytest.mark.parametrize("seed,L,N,D", [(51, 30, 600, 72), (52, 8, 300, 8)])
-def test_reverse_scan_vs_oracle(gpu_lib, seed, L, N, D):
+@pytest.mark.parametrize("seed,L,N,D,quad", [(51, 30, 600, 72, "gauss3"), (52, 8, 300, 8, "gauss3"),
+                                             (53, 30, 600, 72, "e2")])
+def test_reverse_scan_vs_oracle(gpu_lib, seed, L, N, D, quad):
     """dL/dkappa_line of the reverse depth scan, elementwise, against the oracle's
     reverse of the formal solution and tau scan (per pixel, relative to the
     largest |dL/dkappa| over depth)."""
     pz = gpu_lib
     wl = W.tiny(seed=seed, L=L, N=N, D=D)
+    wl.quadrature = quad
     rng = np.random.default_rng(seed)
     s = rng.normal(size=N).astype(np.float32)
     plan = pz.plan_for(wl)

@@ -103,29 +103,31 @@ def test_tile_width_invariance(gpu_lib, tile):
 
 
 # -------------------------------------------------------- formal solution
-def _formal(pz, S, tau):
+def _formal(pz, S, tau, quad=0):
     St = torch.as_tensor(S.astype(np.float32), device="cuda").contiguous()
     Tt = torch.as_tensor(tau.astype(np.float32), device="cuda").contiguous()
     F = torch.empty(S.shape[1], dtype=torch.float32, device="cuda")
-    pz.pz_debug_formal_solve(St, Tt, F)
+    pz.pz_debug_formal_solve(St, Tt, F, quadrature=quad)
     torch.cuda.synchronize()
     return F.cpu().numpy().astype(np.float64)
 
 
-def test_formal_solution_linear_source(gpu_lib):
-    """S = a + b tau => F = pi (a + 2b/3) exactly (Eqs. 7-8)."""
+@pytest.mark.parametrize("quad", [0, 1])
+def test_formal_solution_linear_source(gpu_lib, quad):
+    """S = a + b tau => F = pi (a + 2b/3) exactly (Eqs. 7-8), Gauss-3 and E2."""
     tau = np.geomspace(1e-4, 50.0, 72)[:, None] * np.array([1.0, 0.3, 3.0, 10.0])[None, :]
     a, b = 2.0, 3.0
-    F = _formal(gpu_lib, a + b * tau, tau)
+    F = _formal(gpu_lib, a + b * tau, tau, quad)
     np.testing.assert_allclose(F, math.pi * (a + 2 * b / 3), rtol=2e-6)
 
 
-def test_formal_solution_milne_eddington(gpu_lib):
+@pytest.mark.parametrize("quad", [0, 1])
+def test_formal_solution_milne_eddington(gpu_lib, quad):
     tc = np.geomspace(1e-4, 60.0, 72)[:, None] * np.ones((1, 4))
     eta = np.array([0.0, 0.3, 5.0, 300.0])[None, :]
     a, b = 1.0, 2.5
     S = a + b * tc
-    ratio = _formal(gpu_lib, S, tc * (1 + eta)) / _formal(gpu_lib, S, tc)
+    ratio = _formal(gpu_lib, S, tc * (1 + eta), quad) / _formal(gpu_lib, S, tc, quad)
     expect = (a + 2 * b / (3 * (1 + eta[0]))) / (a + 2 * b / 3)
     np.testing.assert_allclose(ratio, expect, rtol=2e-6)
 
@@ -134,7 +136,18 @@ def test_formal_solution_curved_source(gpu_lib):
     """A curved source against the oracle's formal solution (same quadrature)."""
     tau = np.geomspace(1e-3, 30.0, 72)[:, None] * np.array([1.0, 2.0])[None, :]
     S = np.exp(-1.0 / (0.3 + tau)) + 0.2 * np.sqrt(tau)
-    np.testing.assert_allclose(_formal(gpu_lib, S, tau), O.flux_gauss3(S, tau), rtol=1e-5)
+    S32, t32 = S.astype(np.float32).astype(np.float64), tau.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(_formal(gpu_lib, S, tau), O.flux_gauss3(S32, t32), rtol=1e-5)
+    np.testing.assert_allclose(_formal(gpu_lib, S, tau, 1), O.flux_e2(S32, t32), rtol=1e-6)
+
+
+def test_flux_500_503nm_e2(gpu_lib):
+    """The E2 form of Eq. 8 on the 500-503 nm case, every pixel vs the oracle."""
+    wl = W.config1()
+    wl.quadrature = "e2"
+    F, Fc = _run_forward(gpu_lib, wl)
+    Fo, Fco = O.synthesize(wl)
+    print("max rel f err (E2)", _flux_close(F, Fc, Fo, Fco))
 
 
 # ------------------------------------------------- full-size, sampled pixels
