@@ -27,6 +27,7 @@ import numpy as np
 N_W = 32
 U_MAX = 30.25
 A_SMALL = 0.15
+A_TINY = 0.03      # a <= A_TINY: the a^5 terms (and the t^4 term of cos 2av) are dropped
 
 
 def weideman(N):
@@ -130,6 +131,14 @@ def fits():
                                                          f32(a * a) * horner32(res["LAM_P4"][0], u))
     H32 = np.exp(a * a - u) * np.cos(2 * a * v) + a * (num / Qv).astype(np.float64)
     res["check_H"] = np.max(np.abs(H32 - H) / H)
+    # the reduced form for a <= A_TINY against the full series at a = A_TINY
+    b = A_TINY
+    Hb = np.exp(b * b - u) * np.cos(2 * b * v) + b * (lam[0] + b * b * lam[1] + b ** 4 * lam[2])
+    t = 4.0 * b * b * u
+    cs3 = 1.0 - t / 2.0 + t * t / 24.0 - t ** 3 / 720.0
+    numb = horner32(res["LAM_P0"][0], u) + f32(b * b) * horner32(res["LAM_P2"][0], u)
+    Hb32 = np.exp(b * b - u) * cs3 + b * (numb / Qv).astype(np.float64)
+    res["check_H_tiny"] = np.max(np.abs(Hb32 - Hb) / Hb)
     return res
 
 
@@ -142,7 +151,10 @@ def main():
     out.append("#define PZ_VOIGT_WING_R2 30.25f   /* |z|^2 below which the core formulas apply */")
     out.append("#define PZ_VOIGT_TIER2_R2 64.0f   /* |z| >= 8: four-node wing */")
     out.append("#define PZ_VOIGT_TIER3_R2 1600.0f /* |z| >= 40: two-node wing */")
-    out.append("#define PZ_VOIGT_A_SMALL %.2ff      /* a <= this: float32 small-damping core */" % A_SMALL)
+    out.append("#define PZ_VOIGT_A2_SMALL %.6ef  /* a^2 <= this (a <= %.2f): float32 small-damping core */"
+               % (A_SMALL ** 2, A_SMALL))
+    out.append("#define PZ_VOIGT_A2_TINY %.6ef   /* a^2 <= this (a <= %.2f): core without the a^5 terms */"
+               % (A_TINY ** 2, A_TINY))
     for n, tag in ((6, "GH6"), (4, "GH4"), (2, "GH2")):
         t, w = np.polynomial.hermite.hermgauss(n)
         pos = t > 0
@@ -151,6 +163,7 @@ def main():
     res = fits()
     out.append("/* small-damping core: max relative error of H at a = %.2f vs the truncated series: %.1e */"
                % (A_SMALL, res["check_H"]))
+    out.append("/* reduced core (no a^5 terms) at a = %.2f vs the full series: %.1e */" % (A_TINY, res["check_H_tiny"]))
     for name in ("LAM_Q", "LAM_P0", "LAM_P2", "LAM_P4", "MU_Q", "MU_P0", "MU_P2", "MU_P4"):
         c, e = res[name]
         out.append(arr("PZ_%s" % name, c) + ("  /* weighted max error %.1e */" % e if e else ""))

@@ -83,16 +83,15 @@ __global__ __launch_bounds__(512) void kb_params(const StarDev* __restrict__ sta
 }
 
 template <int WPX>
-__global__ __launch_bounds__(512) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
-    __shared__ float4 s_lp[MAX_CHUNK * MAXD];
-    __shared__ LineLds s_ln[MAX_CHUNK];
+__global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
+    __shared__ OpacityLds<WPX> sm;
     __shared__ int s_it;
     for (;;) {
         const int it = next_item(ctr, &s_it);
         if (it >= n) return;
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX>(s, w.y, s.chunk, s_lp, s_ln);
+        dev_opacity_tile<WPX>(s, w.y, s.chunk, sm);
     }
 }
 

@@ -75,7 +75,7 @@ struct StarDev {
     float* g_xi;
     // plan workspaces
     double* pop;                 // [S][2][D] n/(rho U) including 10^dA
-    float4* lp;                  // [L][D] (s = c/dv, a, K, a^2)
+    float4* lp;                  // [L][D] (c/dv, a^2, K, K a)
     float* kappa;                // [D][Npad]
     float* gk;                   // [D][Npad] dL/dkappa_line
     float* gline;                // [3][L] per-line sums (sorted order)

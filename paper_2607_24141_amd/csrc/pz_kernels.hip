@@ -21,9 +21,8 @@ __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
 // (band clusters), and a one-shot grid of ~N/TPX workgroups leaves a long
 // tail of heavy tiles.
 template <int WPX>
-__global__ __launch_bounds__(512) void k_opacity(StarDev s, int chunk) {
-    __shared__ float4 s_lp[MAX_CHUNK * MAXD];
-    __shared__ LineLds s_ln[MAX_CHUNK];
+__global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
+    __shared__ OpacityLds<WPX> sm;
     __shared__ int s_it;
     for (;;) {
         if (threadIdx.x == 0) s_it = atomicAdd(s.qctr, 1);
@@ -31,7 +30,7 @@ __global__ __launch_bounds__(512) void k_opacity(StarDev s, int chunk) {
         const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= s.n_tiles) return;
-        dev_opacity_tile<WPX>(s, s.tile_order[it], chunk, s_lp, s_ln);
+        dev_opacity_tile<WPX>(s, s.tile_order[it], chunk, sm);
     }
 }
 

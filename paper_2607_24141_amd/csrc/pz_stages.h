@@ -47,7 +47,7 @@ __device__ __forceinline__ void dev_populations(const StarDev& s, int idx) {
 //   dv = sqrt(2kT/m + xi^2),  dnu_D = dv / lambda_l
 //   a  = 10^ddamp (g_rad + g_S n_e + g_vdW n_pert) / (4 pi dnu_D)
 //   K  = (pi e^2/m_e c) n/(rho U) 10^(loggf+dgf) e^{-E/kT} (1 - e^{-h nu_l/kT}) / (sqrt(pi) dnu_D)
-// stored as (c/dv, a, K, a^2); v = (lambda_l/lambda_i - 1) c/dv.
+// stored as (c/dv, a^2, K, K a); v = (lambda_l/lambda_i - 1) c/dv.
 __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
     if (idx >= (long)s.L * s.D) return;
     const int l = (int)(idx / s.D), j = (int)(idx - (long)l * s.D);
@@ -68,7 +68,7 @@ __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
     const double strength = line_const * s.pop[spion * s.D + j] * exp10(loggf) *
                             exp(-s.ln.E_eV[l] * EV_ERG / kT) * (-expm1(-H_PLANCK * C_LIGHT / (lam * kT)));
     const double K = strength * lam / (sqrt(PI) * dv);
-    s.lp[idx] = make_float4((float)(C_LIGHT / dv), (float)a, (float)K, (float)(a * a));
+    s.lp[idx] = make_float4((float)(C_LIGHT / dv), (float)(a * a), (float)K, (float)(K * a));
 }
 
 // x = lambda_l / lambda_i - 1 = expm1(delta - k h), k = i - ic: the
@@ -82,35 +82,53 @@ __device__ __forceinline__ float detuning(int k, float delta, float h_hi, float 
 
 // -------------------------------------------------------------- opacity
 // A workgroup of 8 wavefronts owns TPX = 8 WPX consecutive pixels x all
-// depths.  Each wavefront covers WPX pixels x NDG = 64/WPX depth groups, so
-// its lanes see nearby detunings (little divergence between the Voigt
-// regions) and a line's window edge masks few lanes.  Thread (px, dg)
-// accumulates depths j = d NDG + dg of its pixel in registers.  The lines
-// overlapping the tile are a contiguous range of the sorted list; their
-// per-depth parameters are staged through LDS in chunks.  No atomics: every
+// depths.  The lines overlapping the tile are a contiguous range of the
+// sorted list; per chunk of lines, their per-depth parameters and the
+// detuning x of every (line, tile pixel) are staged in LDS (x = kNoLine
+// outside the line's window; real detunings satisfy |x| < 1e-2).
+//
+// Depths split as D = nfull NDG + r, NDG = 64/WPX.  Main part: wavefront w
+// covers pixels w WPX .. w WPX + WPX-1 of the tile, lane (px, dg) depths
+// j = d NDG + dg, d < nfull -- nearby detunings, so little divergence between
+// Voigt regions.  Tail: the TPX x r remaining (pixel, depth) pairs are dealt
+// to the first wavefronts 64 at a time (pixel t / r, depth nfull NDG + t % r),
+// so no lane idles on a partial depth group.  No atomics: every
 // (pixel, depth) sum is owned by one thread and runs in sorted-line order.
 static constexpr int MAX_CHUNK = 16;
+static constexpr float kNoLine = 2.0f;
 
-struct alignas(16) LineLds {
-    float delta;
-    int ic, ilo, ihi;
+// The opacity loop is VALU-issue bound, so resident wavefronts matter more
+// than the few spills a register cap costs (they fall in the per-tile and
+// per-chunk code, not the evaluation loop): 8 waves per SIMD for 4-pixel
+// wavefronts, 6 for the wider ones.
+#define PZ_OPACITY_WAVES(WPX) __attribute__((amdgpu_waves_per_eu((WPX) == 4 ? 8 : 6)))
+
+template <int WPX>
+struct OpacityLds {
+    float4 lp[MAX_CHUNK * MAXD];
+    float x[MAX_CHUNK * 8 * WPX];
 };
 
 // Called by all 512 threads of a workgroup (it synchronises the workgroup).
 template <int WPX>
-__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, float4* s_lp, LineLds* s_ln) {
+__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
     constexpr int NDG = 64 / WPX;
-    constexpr int DPT = (MAXD + NDG - 1) / NDG;
+    constexpr int DPT = MAXD / NDG;                    // most full depth groups
     constexpr int TPX = 8 * WPX;
     const int tid = threadIdx.x;
     const int lane = tid % 64;
-    const int px = lane % WPX;
+    const int wave = tid / 64;
+    const int px = wave * WPX + lane % WPX;           // main pixel within the tile
     const int dg = lane / WPX;
-    const int w0 = tile * TPX + (tid / 64) * WPX;   // first pixel of this wavefront
-    const int i = w0 + px;
     const int D = s.D;
+    const int nfull = D / NDG, r = D - nfull * NDG;
+    const int t = tid;                                 // tail slot
+    const bool tail = t < TPX * r;
+    const int tpx = tail ? t / r : 0;
+    const int tj = nfull * NDG + (tail ? t - tpx * r : 0);
+    const int p0 = tile * TPX;
     const int l0 = s.tile_first[tile], l1 = s.tile_last[tile];
-    float acc[DPT];
+    float acc[DPT], acc_t = 0.0f;
 #pragma unroll
     for (int d = 0; d < DPT; ++d) acc[d] = 0.0f;
 
@@ -119,42 +137,45 @@ __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int
         const float4* src = s.lp + (size_t)c0 * D;
         for (int k = tid; k < nc * D; k += 512) {
             const int q = k / D;
-            s_lp[q * MAXD + (k - q * D)] = src[k];
+            sm.lp[q * MAXD + (k - q * D)] = src[k];
         }
-        if (tid < nc) {
-            LineLds t;
-            t.delta = s.ln.delta[c0 + tid];
-            t.ic = s.ln.ic[c0 + tid];
-            t.ilo = s.ln.ilo[c0 + tid];
-            t.ihi = s.ln.ihi[c0 + tid];
-            s_ln[tid] = t;
+        for (int k = tid; k < nc * TPX; k += 512) {
+            const int q = k / TPX, i = p0 + (k - q * TPX);
+            const int l = c0 + q;
+            float x = kNoLine;
+            if (i >= s.ln.ilo[l] && i <= s.ln.ihi[l]) x = detuning(i - s.ln.ic[l], s.ln.delta[l], s.h_hi, s.h_lo);
+            sm.x[k] = x;
         }
         __syncthreads();
         for (int q = 0; q < nc; ++q) {
-            const LineLds ln = s_ln[q];
-            if (i >= ln.ilo && i <= ln.ihi) {
-                const float x = detuning(i - ln.ic, ln.delta, s.h_hi, s.h_lo);
-                const float4* row = s_lp + q * MAXD;
+            const float4* row = sm.lp + q * MAXD;
+            const float x = sm.x[q * TPX + px];
+            if (x < 1.0f) {
 #pragma unroll
                 for (int d = 0; d < DPT; ++d) {
-                    const int j = d * NDG + dg;
-                    if (j < D) {
-                        const float4 p = row[j];
-                        const float v = x * p.x;
-                        acc[d] = fmaf(p.z, voigt_H(p.y, p.w, v, v * v), acc[d]);
+                    if (d < nfull) {
+                        const float4 p = row[d * NDG + dg];
+                        acc[d] = voigt_acc(acc[d], p.y, p.z, p.w, x * p.x);
                     }
+                }
+            }
+            if (tail) {
+                const float xt = sm.x[q * TPX + tpx];
+                if (xt < 1.0f) {
+                    const float4 p = row[tj];
+                    acc_t = voigt_acc(acc_t, p.y, p.z, p.w, xt * p.x);
                 }
             }
         }
         __syncthreads();
     }
+    const int i = p0 + px;
     if (i < s.N) {
 #pragma unroll
-        for (int d = 0; d < DPT; ++d) {
-            const int j = d * NDG + dg;
-            if (j < D) s.kappa[(size_t)j * s.Npad + i] = acc[d];
-        }
+        for (int d = 0; d < DPT; ++d)
+            if (d < nfull) s.kappa[(size_t)(d * NDG + dg) * s.Npad + i] = acc[d];
     }
+    if (tail && p0 + tpx < s.N) s.kappa[(size_t)tj * s.Npad + p0 + tpx] = acc_t;
 }
 
 // ------------------------------------------------------- formal solution
@@ -663,13 +684,13 @@ __device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane) {
                 const int j = d * NDG + dg;
                 if (j < D) {
                     const float4 q = lp[j];
-                    const float gK = g[(size_t)j * s.Npad] * q.z;
+                    const float gj = g[(size_t)j * s.Npad];
                     const float v = x * q.x;
-                    float H, aHa, X;
-                    voigt_HD(q.y, q.w, v, v * v, H, aHa, X);
-                    sgf = fmaf(gK, H, sgf);
-                    sd = fmaf(gK, aHa, sd);
-                    sxi = fmaf(-gK * X, xi_f * q.x * q.x, sxi);
+                    float KH, KaHa, KX;
+                    voigt_KHD(q.y, q.z, q.w, v, v * v, KH, KaHa, KX);
+                    sgf = fmaf(gj, KH, sgf);
+                    sd = fmaf(gj, KaHa, sd);
+                    sxi = fmaf(-gj * KX, xi_f * q.x * q.x, sxi);
                 }
             }
         }
