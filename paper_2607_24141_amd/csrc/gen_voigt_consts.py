@@ -17,6 +17,12 @@ Regions of z = v + i a (float32 unless noted):
   function of u fitted here on [0, 30.25]; reference values from mpmath at
   40 digits.  The Gaussian part carries the exact real-axis value, so H keeps
   its relative accuracy where exp(-v^2) and the damping term are comparable.
+  The opacity kernel evaluates the same series for H with piecewise
+  polynomials instead: |v| in [0, 5.5] is cut into PW_N intervals, and on
+  each the damping terms Lam0, Lam2, Lam4 are Chebyshev interpolants of
+  degree 5, 4, 2 in t = |v| - (interval centre), stored as monomial
+  coefficients (16 floats per interval, read from LDS): no division and
+  short Horner chains.
 * core with larger damping: Weideman's 32-term rational expansion of w(z)
   (J.A.C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497) in float64.
 
@@ -142,6 +148,62 @@ def fits():
     return res
 
 
+PW_N = 16
+PW_DEG = (5, 4, 2)
+
+
+def pw_tables():
+    """Per interval k of |v| in [0, U_MAX^(1/2)]: [A0..A3 | A4 A5 B0 B1 | B2 B3 B4 c | C0 C1 C2 0]
+    with Lam0 ~ sum A_n t^n, Lam2 ~ sum B_n t^n, Lam4 ~ sum C_n t^n, t = |v| - c."""
+    vmax = np.sqrt(U_MAX)
+    h = vmax / PW_N
+    sp = 2.0 / np.sqrt(np.pi)
+    tab = np.zeros((PW_N, 16))
+    for k in range(PW_N):
+        c = (k + 0.5) * h
+        coefs = []
+        for i, d in enumerate(PW_DEG):
+            x = np.cos((2 * np.arange(d + 1) + 1) * np.pi / (2 * (d + 1)))
+            t = 0.5 * h * x
+            F = dawson_derivs(c + t)
+            y = [-sp * F[1], sp * F[3] / 6.0, -sp * F[5] / 120.0][i]
+            coefs.append(np.linalg.solve(np.vander(t, d + 1, increasing=True), y))
+        A, B, Cc = coefs
+        tab[k] = [A[0], A[1], A[2], A[3], A[4], A[5], B[0], B[1], B[2], B[3], B[4], c, Cc[0], Cc[1], Cc[2], 0.0]
+    return h, tab
+
+
+def pw_check(h, tab):
+    """Max relative error of the float32 piecewise H against wofz for a in (0, A_SMALL]."""
+    from scipy.special import wofz
+    f32 = np.float32
+    t32 = tab.astype(f32)
+    worst = {}
+    for a, full in ((A_SMALL, True), (0.1, True), (A_TINY, False), (1e-2, False), (1e-3, False), (1e-5, False)):
+        v = np.linspace(0.0, np.sqrt(U_MAX), 20001)[:-1]
+        v = v[v * v + a * a < U_MAX]
+        av = v.astype(f32)
+        k = np.minimum((av * f32(1.0 / h)).astype(np.int32), PW_N - 1)
+        T = t32[k]
+        t = av - T[:, 11]
+        L0 = T[:, 5]
+        for n in (4, 3, 2, 1, 0):
+            L0 = L0 * t + T[:, n]
+        L2 = T[:, 10]
+        for n in (9, 8, 7, 6):
+            L2 = L2 * t + T[:, n]
+        L4 = (T[:, 14] * t + T[:, 13]) * t + T[:, 12]
+        a2 = f32(a * a)
+        num = L0 + a2 * (L2 + a2 * L4) if full else L0 + a2 * L2
+        u = av * av
+        tt = f32(4) * a2 * u
+        cs = 1 - tt / 2 + tt * tt / 24 - tt ** 3 / 720 + (tt ** 4 / 40320 if full else 0)
+        H = np.exp(a2 - u).astype(np.float64) * cs + a * num.astype(np.float64)
+        ref = wofz(v + 1j * a).real
+        worst[a] = np.max(np.abs(H - ref) / ref)
+    return worst
+
+
 def arr(name, c, typ="float", fmt="%.9ef"):
     return "__device__ static constexpr %s %s[%d] = {%s};" % (typ, name, len(c), ", ".join(fmt % x for x in c))
 
@@ -167,6 +229,17 @@ def main():
     for name in ("LAM_Q", "LAM_P0", "LAM_P2", "LAM_P4", "MU_Q", "MU_P0", "MU_P2", "MU_P4"):
         c, e = res[name]
         out.append(arr("PZ_%s" % name, c) + ("  /* weighted max error %.1e */" % e if e else ""))
+    h, tab = pw_tables()
+    worst = pw_check(h, tab)
+    out.append("/* piecewise core for the opacity: %d intervals of |v|, degrees %s; max relative error of H"
+               % (PW_N, PW_DEG))
+    out.append("   against wofz (float32 evaluation, includes the float32 exp): %s */"
+               % ", ".join("a=%g: %.1e" % (k, v) for k, v in worst.items()))
+    out.append("static constexpr int PZ_PW_N = %d;" % PW_N)
+    out.append("#define PZ_PW_INV_H %.9ef" % (1.0 / h))
+    out.append("__device__ static constexpr float PZ_PW_TAB[%d] = {" % (PW_N * 16))
+    out += ["    " + ", ".join("%.9ef" % x for x in row) + "," for row in tab]
+    out.append("};")
     L, c = weideman(N_W)
     out.append("static constexpr int PZ_WEID_N = %d;" % N_W)
     out.append("#define PZ_WEID_L %.17e" % L)

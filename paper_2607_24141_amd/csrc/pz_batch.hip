@@ -86,6 +86,7 @@ template <int WPX>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     __shared__ OpacityLds<WPX> sm;
     __shared__ int s_it;
+    load_pw_table(sm.pw);                              // visible after the first item fetch's barrier
     for (;;) {
         const int it = next_item(ctr, &s_it);
         if (it >= n) return;

@@ -24,6 +24,7 @@ template <int WPX>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
     __shared__ OpacityLds<WPX> sm;
     __shared__ int s_it;
+    load_pw_table(sm.pw);                              // visible after the first item fetch's barrier
     for (;;) {
         if (threadIdx.x == 0) s_it = atomicAdd(s.qctr, 1);
         __syncthreads();

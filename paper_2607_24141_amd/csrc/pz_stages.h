@@ -107,9 +107,11 @@ template <int WPX>
 struct OpacityLds {
     float4 lp[MAX_CHUNK * MAXD];
     float x[MAX_CHUNK * 8 * WPX];
+    float4 pw[PZ_PW_N * 4];                           // piecewise core table
 };
 
-// Called by all 512 threads of a workgroup (it synchronises the workgroup).
+// Called by all 512 threads of a workgroup (it synchronises the workgroup);
+// sm.pw must hold the piecewise core table.
 template <int WPX>
 __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
     constexpr int NDG = 64 / WPX;
@@ -155,7 +157,7 @@ __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int
                 for (int d = 0; d < DPT; ++d) {
                     if (d < nfull) {
                         const float4 p = row[d * NDG + dg];
-                        acc[d] = voigt_acc(acc[d], p.y, p.z, p.w, x * p.x);
+                        acc[d] = voigt_acc(acc[d], p.y, p.z, p.w, x * p.x, sm.pw);
                     }
                 }
             }
@@ -163,7 +165,7 @@ __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int
                 const float xt = sm.x[q * TPX + tpx];
                 if (xt < 1.0f) {
                     const float4 p = row[tj];
-                    acc_t = voigt_acc(acc_t, p.y, p.z, p.w, xt * p.x);
+                    acc_t = voigt_acc(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw);
                 }
             }
         }

@@ -13,8 +13,9 @@
 //    are summed over one common denominator.
 //  * core, |z| < 5.5 and a <= 0.15 (float32): the series of w(v + ia) in a
 //    about the real axis, w = exp(-z^2) + (2i/sqrt(pi)) F(z) with F Dawson's
-//    integral; the Gaussian part is exact, the derivatives of F are rational
-//    fits in u (see gen_voigt_consts.py).  For a <= 0.03 the a^5 terms are
+//    integral; the Gaussian part is exact.  The derivatives of F are
+//    piecewise polynomials in |v| for H alone (opacity) and rational fits in u
+//    where L = Im w is needed too (adjoint); see gen_voigt_consts.py.  For a <= 0.03 the a^5 terms are
 //    below 5e-8 of H and are dropped (chosen per wavefront).
 //  * core, |z| < 5.5 and a > 0.15 (float64): Weideman's 32-term rational
 //    expansion of w(z); rare (deep layers of strongly damped lines).
@@ -118,12 +119,32 @@ __device__ __forceinline__ float mu_num(float a2, float u) {
     return fmaf(a2, inner, horner<7>(PZ_MU_P0, u));
 }
 
-// acc + K H, K H = K exp(a^2 - u) cos(2av) + K a Lam(u) / Q(u)
+// acc + K H on the small-damping core from the piecewise table pw (in LDS):
+// K H = K exp(a^2 - u) cos(2av) + K a [Lam0 + a^2 Lam2 (+ a^4 Lam4)](|v|),
+// each Lam a polynomial in t = |v| - c_k on the interval k holding |v|.
 template <bool FULL>
-__device__ __forceinline__ float coreS_KH_acc(float acc, float a2, float K, float Ka, float u) {
+__device__ __forceinline__ float coreP_KH_acc(float acc, float a2, float K, float Ka, float v, const float4* pw) {
+    const float av = fabsf(v);
+    const int k = min((int)(av * PZ_PW_INV_H), PZ_PW_N - 1);
+    const float4* T = pw + 4 * k;
+    const float4 q0 = T[0], q1 = T[1], q2 = T[2];
+    const float t = av - q2.w;
+    const float L0 = fmaf(fmaf(fmaf(fmaf(fmaf(q1.y, t, q1.x), t, q0.w), t, q0.z), t, q0.y), t, q0.x);
+    float inner = fmaf(fmaf(fmaf(fmaf(q2.z, t, q2.y), t, q2.x), t, q1.w), t, q1.z);
+    if (FULL) {
+        const float4 q3 = T[3];
+        inner = fmaf(a2, fmaf(fmaf(q3.z, t, q3.y), t, q3.x), inner);
+    }
+    const float u = v * v;
     const float g = __expf(a2 - u);
-    const float cs = cos_t<FULL>((4.0f * a2) * u);
-    return fmaf(Ka * lam_num<FULL>(a2, u), __builtin_amdgcn_rcpf(horner<9>(PZ_LAM_Q, u)), fmaf(K * g, cs, acc));
+    return fmaf(Ka, fmaf(a2, inner, L0), fmaf(K * g, cos_t<FULL>((4.0f * a2) * u), acc));
+}
+
+// Copies the piecewise core table into LDS (all threads of the workgroup;
+// the caller synchronises before use).
+__device__ __forceinline__ void load_pw_table(float4* dst) {
+    float* d = reinterpret_cast<float*>(dst);
+    for (int k = threadIdx.x; k < PZ_PW_N * 16; k += blockDim.x) d[k] = PZ_PW_TAB[k];
 }
 
 // K H as above and K a L, with L = Im w = -exp(a^2-u) sin(2av) + v Mu(u)/Q'(u):
@@ -167,8 +188,8 @@ __device__ __forceinline__ void core_w(double a, double v, double& wr, double& w
 // __all is wavefront-uniform; the tests run in order of how often each tier
 // is taken in the far-wing-dominated windows of the workloads.
 
-// acc + K H(a, v).
-__device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float Ka, float v) {
+// acc + K H(a, v); pw is the piecewise core table in LDS.
+__device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float Ka, float v, const float4* pw) {
     const float z2 = fmaf(v, v, a2);
     if (__all(z2 >= PZ_VOIGT_TIER2_R2)) {
         if (__any(z2 < PZ_VOIGT_TIER3_R2)) return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
@@ -178,9 +199,8 @@ __device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float K
     // a wavefront with at least one core lane
     if (z2 < PZ_VOIGT_WING_R2) {
         if (a2 <= PZ_VOIGT_A2_SMALL) {
-            const float u = v * v;
-            if (__any(a2 > PZ_VOIGT_A2_TINY)) return coreS_KH_acc<true>(acc, a2, K, Ka, u);
-            return coreS_KH_acc<false>(acc, a2, K, Ka, u);
+            if (__any(a2 > PZ_VOIGT_A2_TINY)) return coreP_KH_acc<true>(acc, a2, K, Ka, v, pw);
+            return coreP_KH_acc<false>(acc, a2, K, Ka, v, pw);
         }
         double wr, wi;
         core_w(sqrt((double)a2), (double)v, wr, wi);
