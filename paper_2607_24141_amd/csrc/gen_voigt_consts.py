@@ -12,17 +12,16 @@ Regions of z = v + i a (float32 unless noted):
   w(v + ia) in powers of a about the real axis,
       w = exp(-z^2) + (2i/sqrt(pi)) F(z),   F = Dawson's integral,
       H = exp(a^2-u) cos(2av) - (2/sqrt(pi)) [a F' - a^3 F'''/6 + a^5 F^(5)/120]
-      L = -exp(a^2-u) sin(2av) + (2/sqrt(pi)) [F - a^2 F''/2 + a^4 F''''/24],
-  with each derivative of F (even ones divided by v) replaced by a rational
-  function of u fitted here on [0, 30.25]; reference values from mpmath at
-  40 digits.  The Gaussian part carries the exact real-axis value, so H keeps
-  its relative accuracy where exp(-v^2) and the damping term are comparable.
-  The opacity kernel evaluates the same series for H with piecewise
-  polynomials instead: |v| in [0, 5.5] is cut into PW_N intervals, and on
-  each the damping terms Lam0, Lam2, Lam4 are Chebyshev interpolants of
-  degree 5, 4, 2 in t = |v| - (interval centre), stored as monomial
-  coefficients (16 floats per interval, read from LDS): no division and
-  short Horner chains.
+      L = -exp(a^2-u) sin(2av) + (2/sqrt(pi)) [F - a^2 F''/2 + a^4 F''''/24].
+  The Gaussian part carries the exact real-axis value, so H keeps its
+  relative accuracy where exp(-v^2) and the damping term are comparable.
+  The damping terms (derivatives of F, the even ones divided by v) are
+  piecewise polynomials: |v| in [0, 5.5] is cut into PW_N intervals, and on
+  each they are Chebyshev interpolants of degree 5, 4, 2 (for the a, a^3,
+  a^5 terms) in t = |v| - (interval centre), from mpmath values at 40
+  digits, stored as monomial coefficients (16 floats per interval, read from
+  LDS): no division and short Horner chains.  For a <= A_TINY the a^5 terms
+  are below 5e-8 of H and are dropped.
 * core with larger damping: Weideman's 32-term rational expansion of w(z)
   (J.A.C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497) in float64.
 
@@ -61,116 +60,39 @@ def dawson_derivs(v):
     return out
 
 
-def ratfit(u, f, m, n, wt, iters=40):
-    """P/Q (deg m, n; Q(0) = 1) minimising the weighted max error (SK + Lawson)."""
-    Qp = np.ones_like(u)
-    w2 = np.ones_like(u)
-    for _ in range(iters):
-        A = np.hstack([np.vstack([u ** k for k in range(m + 1)]).T,
-                       -(f[:, None]) * np.vstack([u ** k for k in range(1, n + 1)]).T])
-        W = (wt * w2 / Qp)[:, None]
-        c, *_ = np.linalg.lstsq(A * W, f * W[:, 0], rcond=None)
-        p, q = c[:m + 1], np.concatenate([[1.0], c[m + 1:]])
-        P, Q = np.polyval(p[::-1], u), np.polyval(q[::-1], u)
-        err = np.abs((P / Q - f) * wt)
-        Qp = Q
-        w2 = w2 * (err / err.max()) ** 0.3 + 1e-12
-        w2 /= w2.max()
-    return p, q, err.max()
-
-
-def horner32(c, u):
-    r = np.zeros_like(u, dtype=np.float32)
-    for x in c[::-1].astype(np.float32):
-        r = r * u.astype(np.float32) + x
-    return r
-
-
-def fit_fixed_q(u, f, q, m, wt, iters=30):
-    """Numerator of degree m for a given denominator q, minimising the weighted max error."""
-    Q = np.polyval(q[::-1], u)
-    A = np.vstack([u ** j for j in range(m + 1)]).T
-    w2 = np.ones_like(u)
-    for _ in range(iters):
-        W = (wt / Q * w2)[:, None]
-        c, *_ = np.linalg.lstsq(A * W, f * Q * W[:, 0], rcond=None)
-        err = np.abs((A @ c / Q - f) * wt)
-        w2 = w2 * (err / err.max()) ** 0.3 + 1e-12
-        w2 /= w2.max()
-    return c, err.max()
-
-
-def fits():
-    """Common-denominator fits: Lam_k = P_k / Q (H terms), Mu_k = R_k / S (L terms)."""
-    v = np.linspace(0.0, np.sqrt(U_MAX), 1501)
-    u = v * v
-    F = dawson_derivs(v)
-    sp = 2.0 / np.sqrt(np.pi)
-    vv = np.where(v > 0, v, 1.0)
-    lam = [-sp * F[1], sp * F[3] / 6.0, -sp * F[5] / 120.0]
-    # odd derivatives divided by v, with their limits at v = 0 (1, -4, 32)
-    mu0 = np.where(v > 0, F[0] / vv, 1.0)
-    mu2 = np.where(v > 0, F[2] / vv, -4.0)
-    mu4 = np.where(v > 0, F[4] / vv, 32.0)
-    mus = [sp * mu0, -sp * mu2 / 2.0, sp * mu4 / 24.0]
-    a = A_SMALL
-    H = np.exp(a * a - u) * np.cos(2 * a * v) + a * (lam[0] + a * a * lam[1] + a ** 4 * lam[2])
-    res = {}
-    p0, q, e0 = ratfit(u, lam[0], 7, 8, a / H)
-    res["LAM_Q"] = (q, 0.0)
-    res["LAM_P0"] = (p0, e0)
-    for k, m in ((1, 8), (2, 7)):
-        c, e = fit_fixed_q(u, lam[k], q, m, a ** (2 * k + 1) / H)
-        res["LAM_P%d" % (2 * k)] = (c, e)
-    Lref = np.abs(-np.exp(a * a - u) * np.sin(2 * a * v) + v * (mus[0] + a * a * mus[1] + a ** 4 * mus[2]))
-    Lw = np.maximum(v, 1e-3) / np.maximum(Lref, 0.05)
-    r0, sq, e0 = ratfit(u, mus[0], 6, 7, Lw)
-    res["MU_Q"] = (sq, 0.0)
-    res["MU_P0"] = (r0, e0)
-    for k, m in ((1, 7), (2, 6)):
-        c, e = fit_fixed_q(u, mus[k], sq, m, a ** (2 * k) * Lw)
-        res["MU_P%d" % (2 * k)] = (c, e)
-    # float32 check of the assembled small-damping H at a = A_SMALL
-    f32 = np.float32
-    Qv = horner32(res["LAM_Q"][0], u)
-    num = horner32(res["LAM_P0"][0], u) + f32(a * a) * (horner32(res["LAM_P2"][0], u) +
-                                                         f32(a * a) * horner32(res["LAM_P4"][0], u))
-    H32 = np.exp(a * a - u) * np.cos(2 * a * v) + a * (num / Qv).astype(np.float64)
-    res["check_H"] = np.max(np.abs(H32 - H) / H)
-    # the reduced form for a <= A_TINY against the full series at a = A_TINY
-    b = A_TINY
-    Hb = np.exp(b * b - u) * np.cos(2 * b * v) + b * (lam[0] + b * b * lam[1] + b ** 4 * lam[2])
-    t = 4.0 * b * b * u
-    cs3 = 1.0 - t / 2.0 + t * t / 24.0 - t ** 3 / 720.0
-    numb = horner32(res["LAM_P0"][0], u) + f32(b * b) * horner32(res["LAM_P2"][0], u)
-    Hb32 = np.exp(b * b - u) * cs3 + b * (numb / Qv).astype(np.float64)
-    res["check_H_tiny"] = np.max(np.abs(Hb32 - Hb) / Hb)
-    return res
-
-
 PW_N = 16
 PW_DEG = (5, 4, 2)
 
 
 def pw_tables():
-    """Per interval k of |v| in [0, U_MAX^(1/2)]: [A0..A3 | A4 A5 B0 B1 | B2 B3 B4 c | C0 C1 C2 0]
-    with Lam0 ~ sum A_n t^n, Lam2 ~ sum B_n t^n, Lam4 ~ sum C_n t^n, t = |v| - c."""
+    """Per interval k of |v| in [0, U_MAX^(1/2)], for the damping terms of H (Lam) and
+    of L/v (Mu): [P0_0..P0_3 | P0_4 P0_5 P2_0 P2_1 | P2_2 P2_3 P2_4 c | P4_0 P4_1 P4_2 0]
+    with P0 ~ sum P0_n t^n (degree 5), P2 (degree 4), P4 (degree 2), t = |v| - c."""
     vmax = np.sqrt(U_MAX)
     h = vmax / PW_N
     sp = 2.0 / np.sqrt(np.pi)
-    tab = np.zeros((PW_N, 16))
+
+    def terms(v):
+        F = dawson_derivs(v)
+        lam = [-sp * F[1], sp * F[3] / 6.0, -sp * F[5] / 120.0]
+        mu = [sp * F[0] / v, -sp * F[2] / (2.0 * v), sp * F[4] / (24.0 * v)]
+        return lam, mu
+
+    tabs = np.zeros((2, PW_N, 16))
     for k in range(PW_N):
         c = (k + 0.5) * h
-        coefs = []
         for i, d in enumerate(PW_DEG):
             x = np.cos((2 * np.arange(d + 1) + 1) * np.pi / (2 * (d + 1)))
-            t = 0.5 * h * x
-            F = dawson_derivs(c + t)
-            y = [-sp * F[1], sp * F[3] / 6.0, -sp * F[5] / 120.0][i]
-            coefs.append(np.linalg.solve(np.vander(t, d + 1, increasing=True), y))
-        A, B, Cc = coefs
-        tab[k] = [A[0], A[1], A[2], A[3], A[4], A[5], B[0], B[1], B[2], B[3], B[4], c, Cc[0], Cc[1], Cc[2], 0.0]
-    return h, tab
+            t = 0.5 * h * x                      # Chebyshev nodes avoid v = 0 exactly
+            lam, mu = terms(c + t)
+            V = np.vander(t, d + 1, increasing=True)
+            for j, y in enumerate((lam[i], mu[i])):
+                co = np.linalg.solve(V, y)
+                slot = (0, 6, 12)[i]
+                tabs[j, k, slot:slot + d + 1] = co
+        tabs[:, k, 11] = c
+    # the layout above puts P2 at slots 6..10 and P4 at 12..14; c at 11
+    return h, tabs[0], tabs[1]
 
 
 def pw_check(h, tab):
@@ -204,6 +126,37 @@ def pw_check(h, tab):
     return worst
 
 
+def pw_check_L(h, tab):
+    """Max error of the float32 piecewise L = Im w relative to |w| (wofz)."""
+    from scipy.special import wofz
+    f32 = np.float32
+    t32 = tab.astype(f32)
+    worst = {}
+    for a, full in ((A_SMALL, True), (0.1, True), (A_TINY, False), (1e-2, False), (1e-3, False)):
+        v = np.linspace(0.0, np.sqrt(U_MAX), 20001)[:-1]
+        v = v[v * v + a * a < U_MAX]
+        av = v.astype(f32)
+        k = np.minimum((av * f32(1.0 / h)).astype(np.int32), PW_N - 1)
+        T = t32[k]
+        t = av - T[:, 11]
+        P0 = T[:, 5]
+        for n in (4, 3, 2, 1, 0):
+            P0 = P0 * t + T[:, n]
+        P2 = T[:, 10]
+        for n in (9, 8, 7, 6):
+            P2 = P2 * t + T[:, n]
+        P4 = (T[:, 14] * t + T[:, 13]) * t + T[:, 12]
+        a2 = f32(a * a)
+        num = P0 + a2 * (P2 + a2 * P4) if full else P0 + a2 * P2
+        u = av * av
+        tt = f32(4) * a2 * u
+        sn = 1 - tt / 6 + tt * tt / 120 - tt ** 3 / 5040 + (tt ** 4 / 362880 if full else 0)
+        L = v * (num.astype(np.float64) - np.exp(a2 - u).astype(np.float64) * 2 * a * sn)
+        ref = wofz(v + 1j * a)
+        worst[a] = np.max(np.abs(L - ref.imag) / np.abs(ref))
+    return worst
+
+
 def arr(name, c, typ="float", fmt="%.9ef"):
     return "__device__ static constexpr %s %s[%d] = {%s};" % (typ, name, len(c), ", ".join(fmt % x for x in c))
 
@@ -222,16 +175,10 @@ def main():
         pos = t > 0
         out.append(arr("PZ_%s_T2" % tag, t[pos] ** 2))
         out.append(arr("PZ_%s_W" % tag, w[pos] * 2.0 / np.pi) + "  /* w_k * 2/pi */")
-    res = fits()
-    out.append("/* small-damping core: max relative error of H at a = %.2f vs the truncated series: %.1e */"
-               % (A_SMALL, res["check_H"]))
-    out.append("/* reduced core (no a^5 terms) at a = %.2f vs the full series: %.1e */" % (A_TINY, res["check_H_tiny"]))
-    for name in ("LAM_Q", "LAM_P0", "LAM_P2", "LAM_P4", "MU_Q", "MU_P0", "MU_P2", "MU_P4"):
-        c, e = res[name]
-        out.append(arr("PZ_%s" % name, c) + ("  /* weighted max error %.1e */" % e if e else ""))
-    h, tab = pw_tables()
+    h, tab, tab_mu = pw_tables()
     worst = pw_check(h, tab)
-    out.append("/* piecewise core for the opacity: %d intervals of |v|, degrees %s; max relative error of H"
+    worst_l = pw_check_L(h, tab_mu)
+    out.append("/* piecewise small-damping core, H terms: %d intervals of |v|, degrees %s; max relative error of H"
                % (PW_N, PW_DEG))
     out.append("   against wofz (float32 evaluation, includes the float32 exp): %s */"
                % ", ".join("a=%g: %.1e" % (k, v) for k, v in worst.items()))
@@ -239,6 +186,11 @@ def main():
     out.append("#define PZ_PW_INV_H %.9ef" % (1.0 / h))
     out.append("__device__ static constexpr float PZ_PW_TAB[%d] = {" % (PW_N * 16))
     out += ["    " + ", ".join("%.9ef" % x for x in row) + "," for row in tab]
+    out.append("};")
+    out.append("/* the same for L = Im w (adjoint): max error of L relative to |w|: %s */"
+               % ", ".join("a=%g: %.1e" % (k, v) for k, v in worst_l.items()))
+    out.append("__device__ static constexpr float PZ_PW_MU_TAB[%d] = {" % (PW_N * 16))
+    out += ["    " + ", ".join("%.9ef" % x for x in row) + "," for row in tab_mu]
     out.append("};")
     L, c = weideman(N_W)
     out.append("static constexpr int PZ_WEID_N = %d;" % N_W)

@@ -86,7 +86,7 @@ template <int WPX>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     __shared__ OpacityLds<WPX> sm;
     __shared__ int s_it;
-    load_pw_table(sm.pw);                              // visible after the first item fetch's barrier
+    load_pw_table(sm.pw, false);                       // visible after the first item fetch's barrier
     for (;;) {
         const int it = next_item(ctr, &s_it);
         if (it >= n) return;
@@ -139,8 +139,10 @@ __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ sta
     }
 }
 
-__global__ __launch_bounds__(512) void kb_gather(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void kb_gather(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     __shared__ int s_it;
+    __shared__ float4 pw[PZ_PW_N * 8];
+    load_pw_table(pw, true);                           // visible after the first item fetch's barrier
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     for (;;) {
         const int it = next_item(ctr, &s_it);
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(512) void kb_gather(const StarDev* __restrict__ sta
         const StarDev& s = stars[w.x];
         for (int q = wave; q < GATHER_ITEM; q += 512 / WAVE) {
             const int l = __builtin_amdgcn_readfirstlane(w.y * GATHER_ITEM + q);
-            dev_gather(s, l, lane);
+            dev_gather(s, l, lane, pw);
         }
     }
 }

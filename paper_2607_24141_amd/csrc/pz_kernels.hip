@@ -24,7 +24,7 @@ template <int WPX>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
     __shared__ OpacityLds<WPX> sm;
     __shared__ int s_it;
-    load_pw_table(sm.pw);                              // visible after the first item fetch's barrier
+    load_pw_table(sm.pw, false);                       // visible after the first item fetch's barrier
     for (;;) {
         if (threadIdx.x == 0) s_it = atomicAdd(s.qctr, 1);
         __syncthreads();
@@ -101,9 +101,12 @@ __global__ __launch_bounds__(64) void k_reverse_scan_e2(StarDev s) {
     dev_reverse_scan_e2<MD>(s, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_gather(StarDev s) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_gather(StarDev s) {
+    __shared__ float4 pw[PZ_PW_N * 8];
+    load_pw_table(pw, true);
+    __syncthreads();
     const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / WAVE) + (int)(threadIdx.x / WAVE));
-    dev_gather(s, l, threadIdx.x % WAVE);
+    dev_gather(s, l, threadIdx.x % WAVE, pw);
 }
 
 __global__ __launch_bounds__(256) void k_scatter_lines(StarDev s) { dev_scatter(s, blockIdx.x * blockDim.x + threadIdx.x); }

@@ -665,8 +665,9 @@ __device__ __forceinline__ float wave_sum(float x) {
     return x;
 }
 
-// One call per wavefront; l must be wavefront-uniform.
-__device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane) {
+// One call per wavefront; l must be wavefront-uniform; pw holds the H and L
+// core tables (LDS).
+__device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, const float4* pw) {
     constexpr int WPX = 8, NDG = 8, DPT = (MAXD + NDG - 1) / NDG;
     if (l >= s.L) return;
     const int px = lane % WPX, dg = lane / WPX;
@@ -689,7 +690,7 @@ __device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane) {
                     const float gj = g[(size_t)j * s.Npad];
                     const float v = x * q.x;
                     float KH, KaHa, KX;
-                    voigt_KHD(q.y, q.z, q.w, v, v * v, KH, KaHa, KX);
+                    voigt_KHD(q.y, q.z, q.w, v, v * v, pw, KH, KaHa, KX);
                     sgf = fmaf(gj, KH, sgf);
                     sd = fmaf(gj, KaHa, sd);
                     sxi = fmaf(-gj * KX, xi_f * q.x * q.x, sxi);

@@ -55,14 +55,20 @@ __device__ __forceinline__ float wing_S(float a2, float z2, const float* T2, con
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-// With P = z2 = u + a^2, C = t_k^2 and h = sum W_k N_k / D_k:
-//   ha = sum W_k (D_k - 2 N_k^2) / D_k^2     (a dH/da = a h + 2 a^3 ha),
-//   x  = sum W_k 2C (C^2 + 2PC - P(3u - a^2)) / D_k^2   (X = H + a dH/da + v dH/dv = a x;
-//        the leading orders of the three terms cancel analytically in the wing).
+// With z2 = u + a^2, C = t_k^2 and h = sum W_k N_k / D_k:
+//   ha = sum W_k M_k / D_k^2,   M_k = D_k - 2 N_k^2 = -z2^2 - C (6 z2 - 4 a^2 + C)
+//        (a dH/da = a h + 2 a^3 ha),
+//   x  = sum W_k 2C Q_k / D_k^2, Q_k = C^2 + 2 C z2 - 3 z2^2 + 4 a^2 z2
+//        (X = H + a dH/da + v dH/dv = a x: the leading orders of the three
+//        terms cancel analytically, so x carries no cancellation).
+// The pair-independent parts of M_k and Q_k are formed once.
 template <int NP>
-__device__ __forceinline__ void wing_SD(float a2, float u, float z2, const float* T2, const float* W, float& h,
-                                        float& ha, float& x) {
-    const float R3 = z2 * (3.0f * u - a2);
+__device__ __forceinline__ void wing_SD(float a2, float z2, const float* T2, const float* W, float& h, float& ha,
+                                        float& x) {
+    const float mz2sq = -z2 * z2;
+    const float E = fmaf(6.0f, z2, -4.0f * a2);
+    const float B = z2 * fmaf(-3.0f, z2, 4.0f * a2);
+    const float z2x2 = z2 + z2;
     h = 0.0f;
     ha = 0.0f;
     x = 0.0f;
@@ -71,24 +77,15 @@ __device__ __forceinline__ void wing_SD(float a2, float u, float z2, const float
         const float C = T2[k];
         const float e = z2 - C;
         const float Dk = fmaf(e, e, (4.0f * C) * a2);
-        const float Nk = z2 + C;
         const float r = __builtin_amdgcn_rcpf(Dk);
+        h = fmaf(fmaf(W[k], z2, W[k] * C), r, h);
         const float r2 = r * r;
-        h = fmaf(W[k] * Nk, r, h);
-        ha = fmaf(W[k] * fmaf(-2.0f * Nk, Nk, Dk), r2, ha);
-        x = fmaf(W[k] * (2.0f * C) * (fmaf(C, C, 2.0f * z2 * C) - R3), r2, x);
+        ha = fmaf(fmaf(-C, E + C, mz2sq), W[k] * r2, ha);
+        x = fmaf(fmaf(C, z2x2 + C, B), (2.0f * W[k] * C) * r2, x);
     }
 }
 
 // ------------------------------------------------------- small-damping core
-template <int N>
-__device__ __forceinline__ float horner(const float* c, float u) {
-    float r = c[N - 1];
-#pragma unroll
-    for (int k = N - 2; k >= 0; --k) r = fmaf(r, u, c[k]);
-    return r;
-}
-
 // cos(2av) and sin(2av)/(2av) as series in t = (2av)^2; FULL keeps the t^4
 // terms (needed up to a = 0.15), else they end at t^3 (a <= 0.03).
 template <bool FULL>
@@ -105,58 +102,69 @@ __device__ __forceinline__ float sinc_t(float t) {
     return fmaf(t, fmaf(t, fmaf(t, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
 }
 
-// Lam(u) = Lam0 + a^2 Lam2 [+ a^4 Lam4]: the damping series of Re w.
-template <bool FULL>
-__device__ __forceinline__ float lam_num(float a2, float u) {
-    const float p2 = horner<9>(PZ_LAM_P2, u);
-    const float inner = FULL ? fmaf(a2, horner<8>(PZ_LAM_P4, u), p2) : p2;
-    return fmaf(a2, inner, horner<8>(PZ_LAM_P0, u));
-}
-template <bool FULL>
-__device__ __forceinline__ float mu_num(float a2, float u) {
-    const float p2 = horner<8>(PZ_MU_P2, u);
-    const float inner = FULL ? fmaf(a2, horner<7>(PZ_MU_P4, u), p2) : p2;
-    return fmaf(a2, inner, horner<7>(PZ_MU_P0, u));
+// Piecewise tables of the small-damping core (in LDS): interval k of |v|
+// holds [P0_0..P0_3 | P0_4 P0_5 P2_0 P2_1 | P2_2 P2_3 P2_4 c | P4_0 P4_1 P4_2 0],
+// four float4 per interval; the table for L follows the one for H.
+struct PwPoint {
+    int k;       // interval
+    float t;     // |v| - centre
+};
+
+__device__ __forceinline__ PwPoint pw_point(float v, const float4* tab) {
+    const float av = fabsf(v);
+    PwPoint p;
+    p.k = min((int)(av * PZ_PW_INV_H), PZ_PW_N - 1);
+    p.t = av - tab[4 * p.k + 2].w;
+    return p;
 }
 
-// acc + K H on the small-damping core from the piecewise table pw (in LDS):
-// K H = K exp(a^2 - u) cos(2av) + K a [Lam0 + a^2 Lam2 (+ a^4 Lam4)](|v|),
-// each Lam a polynomial in t = |v| - c_k on the interval k holding |v|.
+// P0 + a^2 P2 [+ a^4 P4] at t on table interval T.
 template <bool FULL>
-__device__ __forceinline__ float coreP_KH_acc(float acc, float a2, float K, float Ka, float v, const float4* pw) {
-    const float av = fabsf(v);
-    const int k = min((int)(av * PZ_PW_INV_H), PZ_PW_N - 1);
-    const float4* T = pw + 4 * k;
+__device__ __forceinline__ float pw_poly(const float4* T, float t, float a2) {
     const float4 q0 = T[0], q1 = T[1], q2 = T[2];
-    const float t = av - q2.w;
-    const float L0 = fmaf(fmaf(fmaf(fmaf(fmaf(q1.y, t, q1.x), t, q0.w), t, q0.z), t, q0.y), t, q0.x);
+    const float P0 = fmaf(fmaf(fmaf(fmaf(fmaf(q1.y, t, q1.x), t, q0.w), t, q0.z), t, q0.y), t, q0.x);
     float inner = fmaf(fmaf(fmaf(fmaf(q2.z, t, q2.y), t, q2.x), t, q1.w), t, q1.z);
     if (FULL) {
         const float4 q3 = T[3];
         inner = fmaf(a2, fmaf(fmaf(q3.z, t, q3.y), t, q3.x), inner);
     }
+    return fmaf(a2, inner, P0);
+}
+
+// acc + K H on the small-damping core:
+// K H = K exp(a^2 - u) cos(2av) + K a [Lam0 + a^2 Lam2 (+ a^4 Lam4)](|v|).
+template <bool FULL>
+__device__ __forceinline__ float coreP_KH_acc(float acc, float a2, float K, float Ka, float v, const float4* pw) {
+    const PwPoint p = pw_point(v, pw);
+    const float lam = pw_poly<FULL>(pw + 4 * p.k, p.t, a2);
     const float u = v * v;
     const float g = __expf(a2 - u);
-    return fmaf(Ka, fmaf(a2, inner, L0), fmaf(K * g, cos_t<FULL>((4.0f * a2) * u), acc));
+    return fmaf(Ka, lam, fmaf(K * g, cos_t<FULL>((4.0f * a2) * u), acc));
 }
 
-// Copies the piecewise core table into LDS (all threads of the workgroup;
-// the caller synchronises before use).
-__device__ __forceinline__ void load_pw_table(float4* dst) {
-    float* d = reinterpret_cast<float*>(dst);
-    for (int k = threadIdx.x; k < PZ_PW_N * 16; k += blockDim.x) d[k] = PZ_PW_TAB[k];
-}
-
-// K H as above and K a L, with L = Im w = -exp(a^2-u) sin(2av) + v Mu(u)/Q'(u):
-//   K a L = v (K a Mu/Q' - 2 a^2 K exp(a^2-u) sin(2av)/(2av)).
+// K H as above and K a L, L = Im w = -exp(a^2-u) sin(2av) + v [Mu0 + a^2 Mu2 (+ a^4 Mu4)](|v|):
+//   K a L = v (K a Mu - 2 a^2 K exp(a^2-u) sin(2av)/(2av)).
 template <bool FULL>
-__device__ __forceinline__ void coreS_KHL(float a2, float K, float Ka, float v, float u, float& KH, float& KaL) {
-    const float g = __expf(a2 - u);
+__device__ __forceinline__ void coreP_KHL(float a2, float K, float Ka, float v, const float4* pw, float& KH,
+                                          float& KaL) {
+    const PwPoint p = pw_point(v, pw);
+    const float lam = pw_poly<FULL>(pw + 4 * p.k, p.t, a2);
+    const float mu = pw_poly<FULL>(pw + 4 * (PZ_PW_N + p.k), p.t, a2);
+    const float u = v * v;
     const float t = (4.0f * a2) * u;
-    KH = fmaf(Ka * lam_num<FULL>(a2, u), __builtin_amdgcn_rcpf(horner<9>(PZ_LAM_Q, u)), K * g * cos_t<FULL>(t));
-    const float Kg = K * g;
-    KaL = v * fmaf(Ka * mu_num<FULL>(a2, u), __builtin_amdgcn_rcpf(horner<8>(PZ_MU_Q, u)),
-                   -2.0f * a2 * Kg * sinc_t<FULL>(t));
+    const float Kg = K * __expf(a2 - u);
+    KH = fmaf(Ka, lam, Kg * cos_t<FULL>(t));
+    KaL = v * fmaf(Ka, mu, -2.0f * a2 * Kg * sinc_t<FULL>(t));
+}
+
+// Copies the piecewise core tables into LDS: the H table, and with_L the L
+// table after it (all threads of the workgroup; the caller synchronises).
+__device__ __forceinline__ void load_pw_table(float4* dst, bool with_L) {
+    float* d = reinterpret_cast<float*>(dst);
+    for (int k = threadIdx.x; k < PZ_PW_N * 16; k += blockDim.x) {
+        d[k] = PZ_PW_TAB[k];
+        if (with_L) d[PZ_PW_N * 16 + k] = PZ_PW_MU_TAB[k];
+    }
 }
 
 // ---------------------------------------------------------------- float64 core
@@ -210,26 +218,27 @@ __device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float K
     return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
 }
 
-// K H, K a dH/da and K X, X = H + a dH/da + v dH/dv.  In the cores these follow
+// K H, K a dH/da and K X, X = H + a dH/da + v dH/dv; pw holds the H and L
+// core tables.  In the cores these follow
 // from w = H + iL: dH/dv = -2(vH - aL), dH/da = 2(vL + aH) - 2/sqrt(pi).
-__device__ __forceinline__ void voigt_KHD(float a2, float K, float Ka, float v, float u, float& KH, float& KaHa,
-                                          float& KX) {
+__device__ __forceinline__ void voigt_KHD(float a2, float K, float Ka, float v, float u, const float4* pw, float& KH,
+                                          float& KaHa, float& KX) {
     const float z2 = u + a2;
     float h, ha, x;
     if (__all(z2 >= PZ_VOIGT_TIER2_R2)) {
         if (__any(z2 < PZ_VOIGT_TIER3_R2))
-            wing_SD<2>(a2, u, z2, PZ_GH4_T2, PZ_GH4_W, h, ha, x);
+            wing_SD<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W, h, ha, x);
         else
-            wing_SD<1>(a2, u, z2, PZ_GH2_T2, PZ_GH2_W, h, ha, x);
+            wing_SD<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W, h, ha, x);
     } else if (!__any(z2 < PZ_VOIGT_WING_R2) || z2 >= PZ_VOIGT_WING_R2) {
-        wing_SD<3>(a2, u, z2, PZ_GH6_T2, PZ_GH6_W, h, ha, x);
+        wing_SD<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W, h, ha, x);
     } else {
         if (a2 <= PZ_VOIGT_A2_SMALL) {
             float KaL;
             if (__any(a2 > PZ_VOIGT_A2_TINY))
-                coreS_KHL<true>(a2, K, Ka, v, u, KH, KaL);
+                coreP_KHL<true>(a2, K, Ka, v, pw, KH, KaL);
             else
-                coreS_KHL<false>(a2, K, Ka, v, u, KH, KaL);
+                coreP_KHL<false>(a2, K, Ka, v, pw, KH, KaL);
             const float c = 2.0f * kInvSqrtPiF * Ka;
             KaHa = fmaf(2.0f, fmaf(v, KaL, a2 * KH), -c);
             KX = fmaf(KH, fmaf(2.0f, a2 - u, 1.0f), fmaf(4.0f * v, KaL, -c));
