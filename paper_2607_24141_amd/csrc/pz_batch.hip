@@ -27,6 +27,7 @@ namespace {
 
 enum Phase {
     PH_POP,        // (star, 512 (species, depth) pairs)
+    PH_LINES,      // (star, 512 lines): per-line factors
     PH_PARAMS,     // (star, PARAM_ITEM (line, depth) pairs)
     PH_OP32,       // (star, tile) of stars with 32-pixel tiles, decreasing cost, atomic queue
     PH_OP64,       // ... 64-pixel tiles
@@ -70,6 +71,13 @@ __global__ __launch_bounds__(512) void kb_pop(const StarDev* __restrict__ stars,
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         dev_populations(stars[w.x], w.y * 512 + threadIdx.x);
+    }
+}
+
+__global__ __launch_bounds__(512) void kb_lines(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = uniform_item(items, it);
+        dev_line_consts(stars[w.x], w.y * 512 + threadIdx.x);
     }
 }
 
@@ -242,6 +250,7 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
         }
         const long nld = (long)s.L * s.D;
         for (int k = 0; k < (s.S * s.D + 511) / 512; ++k) items[PH_POP].push_back({b, k});
+        for (int k = 0; k < (s.L + 511) / 512; ++k) items[PH_LINES].push_back({b, k});
         for (long k = 0; k < (nld + PARAM_ITEM - 1) / PARAM_ITEM; ++k) items[PH_PARAMS].push_back({b, (int)k});
         const int ph_op = s.tile_px == 32 ? PH_OP32 : (s.tile_px == 64 ? PH_OP64 : PH_OP128);
         for (int t = 0; t < s.n_tiles; ++t) items[ph_op].push_back({b, t});
@@ -339,6 +348,7 @@ int synth_batch(const pz_batch* bt, int32_t mode, pz_stream stream) {
     int2* const* it = bt->items;
     kb_reset<<<1, 64, 0, st>>>(bt->ctr, N_COUNTER);
     kb_pop<<<grid(bt->grid512, n[PH_POP]), 512, 0, st>>>(bt->stars, it[PH_POP], n[PH_POP]);
+    if (n[PH_LINES]) kb_lines<<<grid(bt->grid512, n[PH_LINES]), 512, 0, st>>>(bt->stars, it[PH_LINES], n[PH_LINES]);
     kb_params<<<grid(bt->grid512, n[PH_PARAMS]), 512, 0, st>>>(bt->stars, it[PH_PARAMS], n[PH_PARAMS]);
     if (n[PH_OP32])
         kb_opacity<4><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32], bt->ctr);

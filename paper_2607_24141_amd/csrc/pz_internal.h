@@ -75,6 +75,8 @@ struct StarDev {
     float* g_xi;
     // plan workspaces
     double* pop;                 // [S][2][D] n/(rho U) including 10^dA
+    double* sdv;                 // [S][D] Doppler velocity width dv (cm/s)
+    double4* lc;                 // [L] per-line factors of K and a (see dev_line_consts)
     float4* lp;                  // [L][D] (c/dv, a^2, K, K a)
     float* kappa;                // [D][Npad]
     float* gk;                   // [D][Npad] dL/dkappa_line
@@ -117,6 +119,8 @@ struct pz_plan {
     int* sp_off;
     int* sp_idx;
     double* pop;
+    double* sdv;
+    double4* lc;
     float4* lp;
     float* kappa;
     float* gk;

@@ -12,6 +12,8 @@ __global__ __launch_bounds__(256) void k_populations(StarDev s) {
     dev_populations(s, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+__global__ __launch_bounds__(256) void k_line_consts(StarDev s) { dev_line_consts(s, blockIdx.x * blockDim.x + threadIdx.x); }
+
 __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
     dev_line_params(s, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
@@ -142,6 +144,7 @@ hipError_t launch_populations(const StarDev& s, hipStream_t st) {
 hipError_t launch_line_params(const StarDev& s, hipStream_t st) {
     const long n = (long)s.L * s.D;
     if (n == 0) return hipSuccess;
+    k_line_consts<<<(s.L + 255) / 256, 256, 0, st>>>(s);
     k_line_params<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(s);
     return hipGetLastError();
 }

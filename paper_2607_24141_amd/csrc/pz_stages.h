@@ -40,35 +40,45 @@ __device__ __forceinline__ void dev_populations(const StarDev& s, int idx) {
     const double n = (s.dA ? exp10((double)s.dA[sp]) : 1.0) * s.n_species[sp * s.D + j];
     s.pop[(sp * 2 + 0) * s.D + j] = n * fI / (s.rho[j] * U0);
     s.pop[(sp * 2 + 1) * s.D + j] = n * fII / (s.rho[j] * U1);
+    // Doppler width (Eq. 5), per species and depth
+    const double xi = (double)s.xi[0] * 1.0e5;
+    s.sdv[sp * s.D + j] = sqrt(2.0 * K_BOLTZ * T / (s.mass[sp] * AMU_G) + xi * xi);
 }
 
 // ------------------------------------------------------ line-depth params
+// Per line (Eqs. 4, 5, 30), in float64:
+//   x = (pi e^2/m_e c) 10^(loggf+dgf) lambda_l / sqrt(pi)
+//   y, z, w = 10^ddamp lambda_l / (4 pi) x (g_rad, g_S, g_vdW)
+__device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
+    if (l >= s.L) return;
+    const int caller = s.ln.perm[l];
+    const double lam = s.ln.lam_cm[l];
+    const double loggf = s.ln.loggf[l] + (s.dgf ? (double)s.dgf[caller] : 0.0);
+    const double line_const = PI * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT);
+    const double damp = (s.ddamp ? exp10((double)s.ddamp[caller]) : 1.0) * lam / (4.0 * PI);
+    s.lc[l] = make_double4(line_const * exp10(loggf) * lam / sqrt(PI), damp * exp10(s.ln.lgr[l]),
+                           damp * exp10(s.ln.lgs[l]), damp * exp10(s.ln.lgw[l]));
+}
+
 // Per (line, depth), in float64 then rounded (Eqs. 4-5, 30):
 //   dv = sqrt(2kT/m + xi^2),  dnu_D = dv / lambda_l
 //   a  = 10^ddamp (g_rad + g_S n_e + g_vdW n_pert) / (4 pi dnu_D)
 //   K  = (pi e^2/m_e c) n/(rho U) 10^(loggf+dgf) e^{-E/kT} (1 - e^{-h nu_l/kT}) / (sqrt(pi) dnu_D)
-// stored as (c/dv, a^2, K, K a); v = (lambda_l/lambda_i - 1) c/dv.
+// stored as (c/dv, a^2, K, K a); v = (lambda_l/lambda_i - 1) c/dv.  The
+// per-line and per-(species, depth) factors come from dev_line_consts and
+// dev_populations.
 __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
     if (idx >= (long)s.L * s.D) return;
     const int l = (int)(idx / s.D), j = (int)(idx - (long)l * s.D);
     const double T = s.T[j];
     const int spion = s.ln.spion[l];
-    const int sp = spion >> 1;
-    const int caller = s.ln.perm[l];
-    const double xi = (double)s.xi[0] * 1.0e5;
-    const double mass = s.mass[sp] * AMU_G;
-    const double dv = sqrt(2.0 * K_BOLTZ * T / mass + xi * xi);
-    const double lam = s.ln.lam_cm[l];
-    double gam = exp10(s.ln.lgr[l]) + exp10(s.ln.lgs[l]) * s.ne[j] + exp10(s.ln.lgw[l]) * s.npert[j];
-    if (s.ddamp) gam *= exp10((double)s.ddamp[caller]);
-    const double a = gam * lam / (4.0 * PI * dv);
-    const double loggf = s.ln.loggf[l] + (s.dgf ? (double)s.dgf[caller] : 0.0);
-    const double line_const = PI * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT);
+    const double inv_dv = 1.0 / s.sdv[(spion >> 1) * s.D + j];
+    const double4 c = s.lc[l];
+    const double a = fma(c.w, s.npert[j], fma(c.z, s.ne[j], c.y)) * inv_dv;
     const double kT = K_BOLTZ * T;
-    const double strength = line_const * s.pop[spion * s.D + j] * exp10(loggf) *
-                            exp(-s.ln.E_eV[l] * EV_ERG / kT) * (-expm1(-H_PLANCK * C_LIGHT / (lam * kT)));
-    const double K = strength * lam / (sqrt(PI) * dv);
-    s.lp[idx] = make_float4((float)(C_LIGHT / dv), (float)(a * a), (float)K, (float)(K * a));
+    const double K = c.x * s.pop[spion * s.D + j] * exp(-s.ln.E_eV[l] * EV_ERG / kT) *
+                     (-expm1(-H_PLANCK * C_LIGHT / (s.ln.lam_cm[l] * kT))) * inv_dv;
+    s.lp[idx] = make_float4((float)(C_LIGHT * inv_dv), (float)(a * a), (float)K, (float)(K * a));
 }
 
 // x = lambda_l / lambda_i - 1 = expm1(delta - k h), k = i - ic: the
