@@ -18,6 +18,11 @@ Steps and the passages they follow (Sec. 2.1 unless noted):
               special function used as one step)
   window      pixel i receives line l iff |lambda_i - lambda_l| <= W
               (the bounded wing span of Sec. 2.2; W fixed by the workload)
+  centre test optional (Sec. 2.2, Table 2): a (line, depth) pair is kept only
+              if its centre opacity reaches eta times the continuum, and a kept
+              pair deposits only within a strength-dependent span |v| <= V
+              (the threshold and the span rule are this implementation's
+              reading; see center_test)
   extinction  Eq. 3 with sigma_c = 0 and a power-law continuum
   tau         d tau = chi dm with the trapezoid rule, tau_0 = chi_0 m_0
   source      Eq. 6 with epsilon = 1: S = B_lambda(T), per nm
@@ -38,7 +43,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import wofz, expn
+from scipy.special import wofz, expn, erfcx
 
 # CODATA 2018
 C_LIGHT = 2.99792458e10          # cm s^-1
@@ -181,6 +186,7 @@ def line_opacity(wl, params=None, pix=None):
         pp, ll = p_idx[b0:b1], l_idx[b0:b1]
         lp, v = _pair_terms(wl, params, pp, ll, pix)
         kap = lp["s"] * voigt(lp["a"], v) / (SQRT_PI * lp["dnu"])
+        kap = kap * _center_mask(wl, lp, wl.lines.lam0_nm[ll][:, None], v)
         np.add.at(out.T, pp, kap)
     return out
 
@@ -190,6 +196,43 @@ def continuum_opacity(wl, pix=None):
     lam = wavelengths_nm(wl.grid, pix)
     a = wl.atm
     return a.kappa0 * (lam / a.lam_ref_nm) ** a.alpha
+
+
+def continuum_at(wl, lam_nm):
+    """The same power-law continuum at arbitrary wavelengths (nm)."""
+    a = wl.atm
+    return a.kappa0 * (np.asarray(lam_nm, np.float64) / a.lam_ref_nm) ** a.alpha
+
+
+def center_test(wl, lp, lam0_nm):
+    """Continuum-referenced centre test and wing span of a (line, depth) pair.
+
+    With R = K / kappa_c(lambda_l), K = s / (sqrt(pi) dnu) the line opacity per
+    unit H, and eta = wl.center_eta:
+      keep  iff  R H(a, 0) >= eta,   H(a, 0) = erfcx(a)   (centre opacity vs continuum)
+      V     =  max( sqrt(ln(R / eta)) if R > eta else 0,  sqrt(a R / (sqrt(pi) eta)) ),
+    the Doppler-core and Lorentz-wing radii at which the profile falls to eta
+    times the continuum.  A kept pair contributes at pixel i iff |v_i| <= V.
+    lp holds [.., D] arrays (s, dnu, a); lam0_nm broadcasts against them.
+    Returns (keep, V) as [.., D] arrays.
+    """
+    eta = wl.center_eta
+    K = lp["s"] / (SQRT_PI * lp["dnu"])
+    R = K / continuum_at(wl, lam0_nm)
+    a = lp["a"]
+    keep = R * erfcx(a) >= eta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        vd = np.sqrt(np.maximum(np.log(R / eta), 0.0))
+    vl = np.sqrt(a * R / (SQRT_PI * eta))
+    return keep, np.maximum(vd, vl)
+
+
+def _center_mask(wl, lp, lam0_nm, v):
+    """1 where the centre test keeps the pair and |v| <= V, else 0; all ones when off."""
+    if not wl.center_eta:
+        return 1.0
+    keep, V = center_test(wl, lp, lam0_nm)
+    return (keep & (np.abs(v) <= V)).astype(np.float64)
 
 
 # ---------------------------------------------------------------------- transfer
@@ -473,6 +516,8 @@ def line_gradients(wl, params, g, pix, line_subset=None, absolute=False):
         t_gf = LN10 * gij * kap
         t_d = LN10 * gij * K * a * Ha
         t_xi = gij * (-K) * (H + a * Ha + v * Hv) * dlndnu_dxi
+        mask = _center_mask(wl, lp, wl.lines.lam0_nm[ll][:, None], v)   # piecewise constant in the parameters
+        t_gf, t_d, t_xi = t_gf * mask, t_d * mask, t_xi * mask
         if absolute:
             t_gf, t_d, t_xi = np.abs(t_gf), np.abs(t_d), np.abs(t_xi)
         np.add.at(Ggf, ll, np.sum(t_gf, axis=1))

@@ -108,6 +108,7 @@ class Workload:
     params: Params
     window_nm: float = WINDOW_NM
     quadrature: str = "gauss3"
+    center_eta: float = 0.0          # continuum-referenced centre test threshold (0: off)
     extra: dict = dataclasses.field(default_factory=dict)
 
 
