@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PZ_VERSION 1
+#define PZ_VERSION 2
 #define PZ_MAX_DEPTH 80
 
 #define PZ_OK 0
@@ -99,6 +99,13 @@ typedef struct {
     int32_t tile_px;            /* opacity tile width in pixels: 0 = autotuned/default */
     int32_t lines_per_chunk;    /* lines staged in LDS per step: 0 = default          */
     int32_t flags;              /* reserved, must be 0                                 */
+    double center_eta;          /* continuum-referenced centre test (Sec. 2.2, Table 2): 0 = off
+                                   (plain windowed sum); eta > 0 keeps a (line, depth) pair only
+                                   if K H(a,0) >= eta kappa_c(lambda_l), and a kept pair deposits
+                                   only where |v| <= max(sqrt(ln(R/eta)), sqrt(a R/(sqrt(pi) eta))),
+                                   R = K / kappa_c(lambda_l); both decided in float64.  Gradients
+                                   treat the mask as constant (it is piecewise constant).  Must be
+                                   finite and >= 0. */
 } pz_options;
 
 /* One fixed 1-D atmosphere (device arrays, float64, caller-owned).  Depth

@@ -48,9 +48,12 @@ class pz_lines(C.Structure):
                 ("log_gstark", _c_double_p), ("log_gvdw", _c_double_p)]
 
 
+ABI_VERSION = 2   # PZ_VERSION of include/pz.h the structures below follow
+
+
 class pz_options(C.Structure):
     _fields_ = [("window_nm", C.c_double), ("quadrature", C.c_int32), ("tile_px", C.c_int32),
-                ("lines_per_chunk", C.c_int32), ("flags", C.c_int32)]
+                ("lines_per_chunk", C.c_int32), ("flags", C.c_int32), ("center_eta", C.c_double)]
 
 
 class pz_atmos(C.Structure):
@@ -82,6 +85,9 @@ def _load():
         raise ImportError("libpz.so is not built (%s); run paper_2607_24141_amd/build.py" % LIB_PATH)
     lib = C.CDLL(LIB_PATH)
     lib.pz_version.restype = C.c_int
+    if lib.pz_version() != ABI_VERSION:
+        raise ImportError("libpz.so reports ABI version %d, this binding needs %d; rebuild with "
+                          "paper_2607_24141_amd/build.py" % (lib.pz_version(), ABI_VERSION))
     lib.pz_last_error.restype = C.c_char_p
     lib.pz_plan_create.argtypes = [C.POINTER(pz_grid), C.POINTER(pz_lines), C.c_int32, C.c_int32,
                                    C.POINTER(pz_options), C.POINTER(C.c_void_p)]
@@ -179,9 +185,10 @@ class Plan:
     """pz_plan_create / pz_plan_destroy around host line arrays (float64)."""
 
     def __init__(self, grid, lines, n_species, n_depth, window_nm=0.3, quadrature=PZ_QUAD_GAUSS3,
-                 tile_px=0, lines_per_chunk=0, flags=0):
+                 tile_px=0, lines_per_chunk=0, flags=0, center_eta=0.0):
         g, ln, keep = c_grid_lines(grid, lines)
-        opts = pz_options(float(window_nm), int(quadrature), int(tile_px), int(lines_per_chunk), int(flags))
+        opts = pz_options(float(window_nm), int(quadrature), int(tile_px), int(lines_per_chunk), int(flags),
+                          float(center_eta))
         h = C.c_void_p()
         _check(lib.pz_plan_create(C.byref(g), C.byref(ln), int(n_species), int(n_depth), C.byref(opts),
                                   C.byref(h)))
@@ -223,6 +230,7 @@ class Plan:
 
 
 def plan_for(workload, **kw):
+    kw.setdefault("center_eta", getattr(workload, "center_eta", 0.0))
     return Plan(workload.grid, workload.lines, workload.atm.S, workload.atm.D,
                 window_nm=workload.window_nm,
                 quadrature=PZ_QUAD_GAUSS3 if workload.quadrature == "gauss3" else PZ_QUAD_E2, **kw)

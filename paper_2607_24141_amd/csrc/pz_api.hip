@@ -120,6 +120,8 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 16;
     if (chunk < 1 || chunk > 16) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 16]");
     if (opts->flags != 0) return fail(PZ_E_INVALID_ARG, "flags must be 0");
+    if (!(opts->center_eta >= 0.0) || !std::isfinite(opts->center_eta))
+        return fail(PZ_E_INVALID_ARG, "center_eta must be finite and >= 0");
     const int L = lines->L, N = grid->N, S = n_species, D = n_depth;
     if (L > 0) {
         if (!lines->lam0_nm || !lines->loggf || !lines->E_eV || !lines->species || !lines->ion ||
@@ -207,7 +209,8 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
                  o_delta = take(Ls * 4), o_ilo = take(Ls * 4), o_ihi = take(Ls * 4), o_perm = take(Ls * 4),
                  o_tf = take((size_t)n_tiles * 4), o_tl = take((size_t)n_tiles * 4),
                  o_spo = take((size_t)(S + 1) * 4), o_spi = take(Ls * 4), o_pop = take((size_t)S * 2 * D * 8),
-                 o_sdv = take((size_t)S * D * 8), o_lc = take(Ls * 32),
+                 o_sdv = take((size_t)S * D * 8), o_lc = take(Ls * 32), o_zmax = take(Ls * D * 4),
+                 o_xlim = take(Ls * 4), o_ikc = take(Ls * 8),
                  o_lp = take(Ls * D * 16), o_kap = take((size_t)D * Npad * 4), o_gk = take((size_t)D * Npad * 4),
                  o_gl = take(Ls * 3 * 4);
     const int n_rchunk = (int)((Ls + RCHUNK - 1) / RCHUNK);
@@ -275,6 +278,10 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->pop = (double*)(base + o_pop);
     p->sdv = (double*)(base + o_sdv);
     p->lc = (double4*)(base + o_lc);
+    p->zmax = (float*)(base + o_zmax);
+    p->xlim = (float*)(base + o_xlim);
+    p->inv_kcl = (double*)(base + o_ikc);
+    p->center_eta = opts->center_eta;
     p->lp = (float4*)(base + o_lp);
     p->kappa = (float*)(base + o_kap);
     p->gk = (float*)(base + o_gk);
@@ -458,6 +465,11 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.pop = p->pop;
     s.sdv = p->sdv;
     s.lc = p->lc;
+    s.zmax = p->zmax;
+    s.xlim = p->xlim;
+    s.inv_kcl = p->inv_kcl;
+    s.center_eta = p->center_eta;
+    s.center = p->center_eta > 0.0;
     s.lp = p->lp;
     s.kappa = p->kappa;
     s.gk = p->gk;

@@ -77,6 +77,11 @@ struct StarDev {
     double* pop;                 // [S][2][D] n/(rho U) including 10^dA
     double* sdv;                 // [S][D] Doppler velocity width dv (cm/s)
     double4* lc;                 // [L] per-line factors of K and a (see dev_line_consts)
+    float* zmax;                 // [L][D] centre test: kept pairs deposit where v^2 + a^2 <= zmax (-1: dropped)
+    float* xlim;                 // [L] centre test: largest |x| any depth of the line reaches (0: none)
+    double* inv_kcl;             // [L] centre test: 1 / kappa_c at the line centre
+    double center_eta;           // centre-test threshold (0: plain windowed sum)
+    bool center;
     float4* lp;                  // [L][D] (c/dv, a^2, K, K a)
     float* kappa;                // [D][Npad]
     float* gk;                   // [D][Npad] dL/dkappa_line
@@ -121,6 +126,10 @@ struct pz_plan {
     double* pop;
     double* sdv;
     double4* lc;
+    float* zmax;
+    float* xlim;
+    double* inv_kcl;
+    double center_eta;
     float4* lp;
     float* kappa;
     float* gk;

@@ -58,6 +58,10 @@ __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
     const double damp = (s.ddamp ? exp10((double)s.ddamp[caller]) : 1.0) * lam / (4.0 * PI);
     s.lc[l] = make_double4(line_const * exp10(loggf) * lam / sqrt(PI), damp * exp10(s.ln.lgr[l]),
                            damp * exp10(s.ln.lgs[l]), damp * exp10(s.ln.lgw[l]));
+    if (s.center) {
+        s.xlim[l] = 0.0f;                                // raised by dev_line_params
+        s.inv_kcl[l] = 1.0 / (s.kappa0 * pow(lam * 1.0e7 / s.lam_ref_nm, s.alpha));   // 1 / kappa_c(lambda_l)
+    }
 }
 
 // Per (line, depth), in float64 then rounded (Eqs. 4-5, 30):
@@ -67,9 +71,13 @@ __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
 // stored as (c/dv, a^2, K, K a); v = (lambda_l/lambda_i - 1) c/dv.  The
 // per-line and per-(species, depth) factors come from dev_line_consts and
 // dev_populations.
+// Every lane of the wavefront must call this (lanes past L*D included):
+// the centre test reduces across the wavefront.
 __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
-    if (idx >= (long)s.L * s.D) return;
-    const int l = (int)(idx / s.D), j = (int)(idx - (long)l * s.D);
+    const long n = (long)s.L * s.D;
+    const bool valid = idx < n;
+    const long id = valid ? idx : n - 1;                  // out-of-range lanes compute a copy, store nothing
+    const int l = (int)(id / s.D), j = (int)(id - (long)l * s.D);
     const double T = s.T[j];
     const int spion = s.ln.spion[l];
     const double inv_dv = 1.0 / s.sdv[(spion >> 1) * s.D + j];
@@ -78,7 +86,36 @@ __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
     const double kT = K_BOLTZ * T;
     const double K = c.x * s.pop[spion * s.D + j] * exp(-s.ln.E_eV[l] * EV_ERG / kT) *
                      (-expm1(-H_PLANCK * C_LIGHT / (s.ln.lam_cm[l] * kT))) * inv_dv;
-    s.lp[idx] = make_float4((float)(C_LIGHT * inv_dv), (float)(a * a), (float)K, (float)(K * a));
+    if (valid) s.lp[idx] = make_float4((float)(C_LIGHT * inv_dv), (float)(a * a), (float)K, (float)(K * a));
+    if (!s.center) return;
+    // continuum-referenced centre test, decided in float64: keep iff
+    // K H(a,0) >= eta kappa_c(lambda_l); a kept pair deposits where
+    // |v| <= V = max(sqrt(ln(R/eta)), sqrt(a R / (sqrt(pi) eta))), R = K / kappa_c
+    const double eta = s.center_eta;
+    const double R = K * s.inv_kcl[l];
+    float zm = -1.0f, xl = 0.0f;
+    if (R * __ocml_erfcx_f64(a) >= eta) {
+        const double vd = R > eta ? sqrt(log(R / eta)) : 0.0;
+        const double V = fmax(vd, sqrt(a * R / (sqrt(PI) * eta)));
+        zm = (float)(V * V + a * a);
+        xl = (float)(V / (C_LIGHT * inv_dv));              // detuning |x| = V dv / c
+    }
+    if (valid) s.zmax[idx] = zm;
+    // Largest |x| over each line's depths: one wavefront-wide max and one
+    // atomic per distinct line in the wavefront (non-negative floats order as
+    // their bit patterns; the result does not depend on the order).
+    const int lane = (int)(threadIdx.x & 63);
+    bool done = !valid || !(xl > 0.0f);
+    for (;;) {
+        const unsigned long long b = __ballot(!done);
+        if (b == 0) break;
+        const int first = __ffsll(b) - 1;
+        const int lc = __shfl(l, first, 64);
+        float m = l == lc ? xl : 0.0f;
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if (lane == first) atomicMax(reinterpret_cast<int*>(&s.xlim[lc]), __float_as_int(m));
+        if (l == lc) done = true;
+    }
 }
 
 // x = lambda_l / lambda_i - 1 = expm1(delta - k h), k = i - ic: the
@@ -116,14 +153,16 @@ static constexpr float kNoLine = 2.0f;
 template <int WPX>
 struct OpacityLds {
     float4 lp[MAX_CHUNK * MAXD];
+    float zmax[MAX_CHUNK * MAXD];                     // centre test only
     float x[MAX_CHUNK * 8 * WPX];
     float4 pw[PZ_PW_N * 4];                           // piecewise core table
 };
 
-// Called by all 512 threads of a workgroup (it synchronises the workgroup);
-// sm.pw must hold the piecewise core table.
-template <int WPX>
-__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
+// With the centre test (CT) a pixel's detuning is marked kNoLine beyond the
+// line's largest span, and a (pixel, depth) lane evaluates only where
+// v^2 + a^2 <= zmax of its (line, depth).
+template <int WPX, bool CT>
+__device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
     constexpr int NDG = 64 / WPX;
     constexpr int DPT = MAXD / NDG;                    // most full depth groups
     constexpr int TPX = 8 * WPX;
@@ -150,24 +189,28 @@ __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int
         for (int k = tid; k < nc * D; k += 512) {
             const int q = k / D;
             sm.lp[q * MAXD + (k - q * D)] = src[k];
+            if (CT) sm.zmax[q * MAXD + (k - q * D)] = s.zmax[(size_t)c0 * D + k];
         }
         for (int k = tid; k < nc * TPX; k += 512) {
             const int q = k / TPX, i = p0 + (k - q * TPX);
             const int l = c0 + q;
             float x = kNoLine;
             if (i >= s.ln.ilo[l] && i <= s.ln.ihi[l]) x = detuning(i - s.ln.ic[l], s.ln.delta[l], s.h_hi, s.h_lo);
+            // the slack keeps every lane the per-depth test would accept
+            if (CT && !(fabsf(x) <= s.xlim[l] * (1.0f + 1e-5f))) x = kNoLine;
             sm.x[k] = x;
         }
         __syncthreads();
         for (int q = 0; q < nc; ++q) {
             const float4* row = sm.lp + q * MAXD;
+            const float* zrow = sm.zmax + q * MAXD;
             const float x = sm.x[q * TPX + px];
             if (x < 1.0f) {
 #pragma unroll
                 for (int d = 0; d < DPT; ++d) {
                     if (d < nfull) {
                         const float4 p = row[d * NDG + dg];
-                        acc[d] = voigt_acc(acc[d], p.y, p.z, p.w, x * p.x, sm.pw);
+                        acc[d] = voigt_acc<CT>(acc[d], p.y, p.z, p.w, x * p.x, sm.pw, CT ? zrow[d * NDG + dg] : 0.0f);
                     }
                 }
             }
@@ -175,7 +218,7 @@ __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int
                 const float xt = sm.x[q * TPX + tpx];
                 if (xt < 1.0f) {
                     const float4 p = row[tj];
-                    acc_t = voigt_acc(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw);
+                    acc_t = voigt_acc<CT>(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw, CT ? zrow[tj] : 0.0f);
                 }
             }
         }
@@ -188,6 +231,16 @@ __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int
             if (d < nfull) s.kappa[(size_t)(d * NDG + dg) * s.Npad + i] = acc[d];
     }
     if (tail && p0 + tpx < s.N) s.kappa[(size_t)tj * s.Npad + p0 + tpx] = acc_t;
+}
+
+// Called by all 512 threads of a workgroup (it synchronises the workgroup);
+// sm.pw must hold the piecewise core table.
+template <int WPX>
+__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
+    if (s.center)
+        opacity_tile_body<WPX, true>(s, tile, chunk, sm);
+    else
+        opacity_tile_body<WPX, false>(s, tile, chunk, sm);
 }
 
 // ------------------------------------------------------- formal solution
@@ -677,14 +730,28 @@ __device__ __forceinline__ float wave_sum(float x) {
 
 // One call per wavefront; l must be wavefront-uniform; pw holds the H and L
 // core tables (LDS).
-__device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, const float4* pw) {
+template <bool CT>
+__device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, const float4* pw) {
     constexpr int WPX = 8, NDG = 8, DPT = (MAXD + NDG - 1) / NDG;
-    if (l >= s.L) return;
     const int px = lane % WPX, dg = lane / WPX;
-    const int ilo = s.ln.ilo[l], ihi = s.ln.ihi[l], ic = s.ln.ic[l];
+    int ilo = s.ln.ilo[l], ihi = s.ln.ihi[l];
+    const int ic = s.ln.ic[l];
     const float delta = s.ln.delta[l];
     const int D = s.D;
     const float4* lp = s.lp + (size_t)l * D;
+    const float* zm = CT ? s.zmax + (size_t)l * D : nullptr;
+    if (CT) {
+        // pixels whose detuning x = expm1(delta - k h) can reach the line's
+        // largest span: |x| <= xl  <=>  delta - k h in [log1p(-xl), log1p(xl)]
+        const double xl = (double)s.xlim[l] * (1.0 + 1e-5);
+        if (!(xl > 0.0)) {
+            ihi = ilo - 1;                                // no depth kept
+        } else if (xl < 1e-2) {
+            const double h = s.h, dl = (double)delta;
+            ilo = max(ilo, ic + (int)floor((dl - log1p(xl)) / h) - 1);
+            ihi = min(ihi, ic + (int)ceil((dl - log1p(-xl)) / h) + 1);
+        }
+    }
     const float xi_f = s.xi[0] * (float)(1.0e10 / (C_LIGHT * C_LIGHT));
     float sgf = 0.0f, sd = 0.0f, sxi = 0.0f;
     for (int p0 = ilo; p0 <= ihi; p0 += WPX) {
@@ -697,8 +764,9 @@ __device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, co
                 const int j = d * NDG + dg;
                 if (j < D) {
                     const float4 q = lp[j];
-                    const float gj = g[(size_t)j * s.Npad];
                     const float v = x * q.x;
+                    if (CT && !(fmaf(v, v, q.y) <= zm[j])) continue;
+                    const float gj = g[(size_t)j * s.Npad];
                     float KH, KaHa, KX;
                     voigt_KHD(q.y, q.z, q.w, v, v * v, pw, KH, KaHa, KX);
                     sgf = fmaf(gj, KH, sgf);
@@ -716,6 +784,14 @@ __device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, co
         s.gline[s.L + l] = (float)LN10 * sd;
         s.gline[2 * s.L + l] = sxi;
     }
+}
+
+__device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, const float4* pw) {
+    if (l >= s.L) return;
+    if (s.center)
+        gather_body<true>(s, l, lane, pw);
+    else
+        gather_body<false>(s, l, lane, pw);
 }
 
 // ----------------------------------------------------------- reductions

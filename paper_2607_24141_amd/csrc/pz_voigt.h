@@ -196,9 +196,13 @@ __device__ __forceinline__ void core_w(double a, double v, double& wr, double& w
 // __all is wavefront-uniform; the tests run in order of how often each tier
 // is taken in the far-wing-dominated windows of the workloads.
 
-// acc + K H(a, v); pw is the piecewise core table in LDS.
-__device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float Ka, float v, const float4* pw) {
+// acc + K H(a, v); pw is the piecewise core table in LDS.  With CT the
+// lane adds nothing unless v^2 + a^2 <= zmax2 (centre-test span).
+template <bool CT>
+__device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float Ka, float v, const float4* pw,
+                                           float zmax2) {
     const float z2 = fmaf(v, v, a2);
+    if (CT && !(z2 <= zmax2)) return acc;
     if (__all(z2 >= PZ_VOIGT_TIER2_R2)) {
         if (__any(z2 < PZ_VOIGT_TIER3_R2)) return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
         return fmaf(Ka, wing_S<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W), acc);

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(pz):
 
 
 def test_version(pz):
-    assert pz.pz_version() == 1
+    assert pz.pz_version() == pz.ABI_VERSION == 2
 
 
 def _lines(pz, L=3, **over):
@@ -61,7 +61,7 @@ def _create(pz, grid=None, lines=None, S=2, D=8, opts=None):
 
 @pytest.mark.parametrize("case,code", [
     ("N", -2), ("R", -1), ("lam", -1), ("D", -2), ("Dbig", -2), ("S", -2), ("W", -1), ("quad", -1),
-    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5)])
+    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5), ("eta", -1), ("eta_nan", -1)])
 def test_plan_validation(pz, case, code):
     import numpy as np
     kw = {}
@@ -85,6 +85,10 @@ def test_plan_validation(pz, case, code):
         kw["opts"] = pz.pz_options(0.3, 0, 48, 0, 0)
     elif case == "flags":
         kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 1)
+    elif case == "eta":
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 0, -1e-3)
+    elif case == "eta_nan":
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 0, float("nan"))
     elif case == "species":
         kw["lines"] = _lines(pz, sp=np.array([0, 5, 0], np.int32))
     elif case == "ion":

@@ -54,11 +54,12 @@ def _stars(pz):
     specs = [dict(seed=41, L=30, N=700, D=72, tile=32), dict(seed=42, L=80, N=1500, D=72, tile=64),
              dict(seed=43, L=10, N=257, D=8, tile=128), dict(seed=44, L=0, N=300, D=72, tile=64),
              dict(seed=45, L=120, N=2500, D=40, tile=64), dict(seed=46, L=55, N=999, D=72, tile=128),
-             dict(seed=47, L=40, N=600, D=72, tile=32, quad="e2")]
+             dict(seed=47, L=40, N=600, D=72, tile=32, quad="e2"), dict(seed=48, L=70, N=1100, D=72, tile=32, eta=1e-3)]
     out = []
     for k, sp in enumerate(specs):
         wl = W.tiny(seed=sp["seed"], L=sp["L"], N=sp["N"], D=sp["D"], S=4, n_molecular=1)
         wl.quadrature = sp.get("quad", "gauss3")
+        wl.center_eta = sp.get("eta", 0.0)
         wl.params = W.random_params(np.random.default_rng(k), wl.lines.L, wl.atm.S, 1.1 + 0.2 * k)
         out.append(Star(pz, wl, sp["tile"], target=(k % 2 == 0), seed=k))
     return out
