@@ -1,0 +1,64 @@
+"""Pins of the stored FP64 oracle reference for the 1500-1700 nm
+differentiation workload (tests/golden/config4_golden.npz, written by
+tests/golden/make_config4_golden.py from the oracle alone).
+
+* The stored oracle adjoint agrees with FP64 central differences of the
+  oracle's own forward synthesis (Richardson-combined steps h and h/2) for
+  20 log gf, 20 damping, 9 abundance and the microturbulence corrections:
+  the definition of the derivative, independent of the adjoint code.  The
+  criterion is relative for gradients at least 1e-2 of the largest and
+  absolute (a fraction of the largest) below that, where a central
+  difference is rounding noise.
+* The stored target and seed are what the oracle gives on re-evaluation at
+  sampled pixels (the chi^2 objective of Sec. 5 on the Eq. 9 ratio).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import synth as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config4_golden.npz")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    return np.load(GOLDEN)
+
+
+def s17_ok(g, fd, rtol, atol_frac):
+    """|g - fd| <= rtol |fd| where |fd| >= 1e-2 max|fd|, else <= atol_frac max|fd|
+    (a central difference of a near-zero gradient is rounding noise)."""
+    gmax = np.max(np.abs(fd))
+    big = np.abs(fd) >= 1e-2 * gmax
+    err = np.abs(np.asarray(g) - fd)
+    return np.where(big, err <= rtol * np.abs(fd), err <= atol_frac * gmax), big
+
+
+def test_adjoint_matches_finite_differences(golden):
+    z = golden
+    fd, fh, adj = z["fd_value"], z["fd_value_half"], z["fd_adjoint"]
+    rich = (4.0 * fh - fd) / 3.0
+    ok, big = s17_ok(adj, rich, 1e-5, 1e-7)
+    assert ok.all(), [(z["fd_kind"][i], int(z["fd_index"][i]), rich[i], adj[i]) for i in np.flatnonzero(~ok)[:5]]
+    assert big.sum() >= 15                       # most of the 50 are well above the noise floor
+    # the two step sizes agree where the difference is resolved: converged, not noise
+    ok_h, _ = s17_ok(fd, fh, 1e-4, 1e-6)
+    assert ok_h.all()
+    assert set(z["fd_kind"]) == {"loggf", "damp", "abund", "xi"}
+
+
+def test_target_and_seed_reproduce(golden):
+    z = golden
+    wl = W.config4()
+    rng = np.random.default_rng(5)
+    pix = np.unique(np.concatenate([[0, wl.grid.N - 1], rng.integers(0, wl.grid.N, 14)]))
+    Ft, Fct = O.synthesize(wl, wl.extra["truth"], pix=pix)
+    y = Ft / Fct + wl.extra["noise"][pix]
+    np.testing.assert_allclose(z["y"][pix], y, rtol=1e-6)
+    F, Fc = O.synthesize(wl, wl.params, pix=pix)
+    dF, _ = O.chi2_seed(F, Fc, z["y"][pix].astype(np.float64), wl.extra["sigma"])
+    scale = np.max(np.abs(z["seed"]))
+    assert np.max(np.abs(z["seed"][pix] - dF)) <= 1e-5 * scale
