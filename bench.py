@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fwd,fwdbwd,batch")
+    ap.add_argument("--modes", default="fwd,fwdbwd,center,batch")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -195,6 +195,32 @@ def main():
         out["fwd_bwd"] = {"spectra_per_s": 1000.0 / ms_fb, "ms_per_step": ms_fb, "ratio_to_fwd": ms_fb / ms_fwd,
                           "voigt_evals_per_s": 2 * plan.voigt_evals / (ms_fb * 1e-3),
                           "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof_fb.items() if v[1]}}
+
+    # ---- the continuum-referenced centre test (a different result by design)
+    if "center" in modes:
+        eta = 1.0e-3
+        log("centre test, eta = %g" % eta)
+        f_plain = (F / Fc).clone()
+        cplan = pz.plan_for(wl, tile_px=plan.tile_px, lines_per_chunk=16, center_eta=eta)
+        cf = lambda: pz.synth_forward(cplan, atm, par, F, Fc)
+        cf()
+        torch.cuda.synchronize()
+        dmax = float(torch.max(torch.abs(F / Fc - f_plain)).item())
+        ms_cf, _ = timed(cf, args.steps, args.warmup, torch)
+        out["center_test"] = {"eta": eta, "fwd_spectra_per_s": 1000.0 / ms_cf, "fwd_ms": ms_cf,
+                              "speedup_vs_plain_fwd": ms_fwd / ms_cf, "max_abs_dflux_vs_plain": dmax}
+        if "fwdbwd" in modes:
+            gFc_ = torch.empty_like(F)
+
+            def cfb():
+                pz.synth_forward(cplan, atm, par, F, Fc)
+                pz.pz_chi2_seed(F, Fc, y, sigma, gF, gFc_, loss)
+                pz.synth_backward(cplan, atm, par, gF, *g)
+
+            ms_cfb, _ = timed(cfb, args.steps, args.warmup, torch)
+            out["center_test"].update({"fwd_bwd_spectra_per_s": 1000.0 / ms_cfb, "fwd_bwd_ms": ms_cfb,
+                                       "speedup_vs_plain_fwd_bwd": out["fwd_bwd"]["ms_per_step"] / ms_cfb})
+        cplan.destroy()
 
     # ---- batched forward + backward over many stars (one captured graph)
     if "batch" in modes:
