@@ -302,3 +302,22 @@ def random_params(rng, L, S, xi, scale=1.0):
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+
+
+def apogee_instrument(grid, R_lsf=(20000.0, 25000.0), vb_max_kms=20.0):
+    """Observed pixels and LSF widths standing in for an APOGEE-like spectrograph
+    on the 1500-1700 nm grid: log-uniform pixels with d(log10 lambda) = 6e-6 over
+    1514-1696 nm in three detector ranges (gaps 1581-1585 and 1644-1647 nm), and
+    a Gaussian LSF whose resolving power runs linearly from R_lsf[0] to R_lsf[1]
+    across the range (sigma in ln lambda = 1 / (2 sqrt(2 ln 2) R)).  The
+    calibration-derived LSF of the paper is not available."""
+    dln = 6.0e-6 * math.log(10.0)
+    x = np.arange(math.log(1514.0), math.log(1696.0), dln)
+    lam = np.exp(x)
+    keep = ~(((lam > 1581.0) & (lam < 1585.0)) | ((lam > 1644.0) & (lam < 1647.0)))
+    lam = lam[keep]
+    lo, hi = grid.lam_first_nm, grid_last(grid)
+    R = R_lsf[0] + (R_lsf[1] - R_lsf[0]) * (lam - lam[0]) / (lam[-1] - lam[0])
+    sigma_ln = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)) * R)
+    assert lam[0] > lo and lam[-1] < hi
+    return lam, sigma_ln, vb_max_kms
