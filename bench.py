@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fwd,fwdbwd,center,batch")
+    ap.add_argument("--modes", default="fwd,fwdbwd,center,instrument,batch")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -221,6 +221,22 @@ def main():
             out["center_test"].update({"fwd_bwd_spectra_per_s": 1000.0 / ms_cfb, "fwd_bwd_ms": ms_cfb,
                                        "speedup_vs_plain_fwd_bwd": out["fwd_bwd"]["ms_per_step"] / ms_cfb})
         cplan.destroy()
+
+    # ---- the instrument operator of Eq. 31 on APOGEE-like pixels (one flux pair)
+    if "instrument" in modes:
+        lam_obs, sig, vbmax = W.apogee_instrument(wl.grid)
+        inst = pz.Instrument(wl.grid, lam_obs, sig, vbmax)
+        vel = torch.tensor([12.0, 6.0], dtype=torch.float32, device=dev)
+        fobs = torch.empty(inst.P, dtype=torch.float32, device=dev)
+        dFi, dFci = torch.empty_like(F), torch.empty_like(F)
+        gv = torch.empty(2, dtype=torch.float32, device=dev)
+        iseed = torch.randn(inst.P, dtype=torch.float32, device=dev)
+        ms_if, _ = timed(lambda: pz.pz_inst_forward(inst, F, Fc, vel, None, None, fobs), args.steps, args.warmup, torch)
+        ms_ib, _ = timed(lambda: pz.pz_inst_backward(inst, F, Fc, vel, iseed, dFi, dFci, gv), args.steps,
+                         args.warmup, torch)
+        out["instrument"] = {"observed_pixels": inst.P, "native_pixels": int(F.numel()),
+                             "fwd_us_per_flux_pair": ms_if * 1e3, "bwd_us_per_flux_pair": ms_ib * 1e3}
+        inst.destroy()
 
     # ---- batched forward + backward over many stars (one captured graph)
     if "batch" in modes:

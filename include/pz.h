@@ -274,6 +274,52 @@ int pz_autotune(const pz_grid* grid, const pz_lines* lines, int32_t n_species, i
                 const pz_options* base, const pz_atmos* atm, const pz_params* par, int32_t reps,
                 pz_options* best, float* best_ms);
 
+/* ---------------------------------------------------------------- instrument
+ * The instrument operator of Eq. 31 (Eq. 9): both native fluxes pass through
+ * a Gaussian broadening B(v_b) on the logarithmic synthesis grid, a Doppler
+ * shift S(v_r) and a Gaussian line-spread function sampled at observed
+ * pixels K before their ratio, f_p = {K S B F}_p / {K S B F_c}_p.
+ * Discretisation (x = ln lambda, native pixel spacing h = ln(1 + 1/R)):
+ *   B: normalised Gaussian of sigma = v_b / (c h) pixels over a fixed support
+ *      of +-J pixels, J = ceil(4 vb_max / (c h)), renormalised at the grid
+ *      ends (v_b below 1e-3 c h acts as the identity, with zero gradient);
+ *   S: value at fractional pixel i - ln(1 + v_r/c)/h by linear interpolation,
+ *      the index clamped to the grid;
+ *   K: normalised Gaussian of the pixel's LSF width in ln lambda over
+ *      |x_i - x_p| <= lsf_trunc widths, sampled at the pixel centre. */
+typedef struct pz_inst pz_inst;     /* opaque */
+
+typedef struct {
+    int32_t P;                  /* observed pixels, >= 1                                    */
+    const double* lam_obs_nm;   /* [P] host: pixel centres (vacuum nm), strictly increasing */
+    const double* lsf_sigma_ln; /* [P] host: Gaussian LSF width in ln lambda (> 0)           */
+    double lsf_trunc;           /* LSF support half-width in widths; 0 = 4                   */
+    double vb_max_kms;          /* > 0: the largest broadening used; sets B's support        */
+} pz_inst_desc;
+
+/* Build an instrument for the synthesis grid: LSF supports (each must lie
+ * inside the grid, and may not shrink from one pixel to the next), their
+ * transposed index ranges, and one device workspace owned by the instrument.
+ * Synchronises.  Errors: PZ_E_INVALID_ARG, PZ_E_SHAPE, PZ_E_NOMEM, PZ_E_HIP. */
+int pz_inst_create(const pz_grid* grid, const pz_inst_desc* desc, pz_inst** out);
+
+/* Release an instrument (NULL is a no-op).  Synchronises the device. */
+void pz_inst_destroy(pz_inst* inst);
+
+/* f = K S B F / K S B Fc.  F, Fc: [N] device float32 native fluxes; vel:
+ * [2] device float32 (v_r, v_b) in km/s; outputs [P] device float32, any of
+ * KF (K S B F), KFc, f may be NULL but not all.  Enqueue-only. */
+int pz_inst_forward(const pz_inst* inst, const float* F, const float* Fc, const float* vel, float* KF, float* KFc,
+                    float* f, pz_stream stream);
+
+/* Vector-Jacobian product of the map above for the seed dL_df [P]: writes
+ * dL_dF, dL_dFc [N] and g_vel [2] = (dL/dv_r, dL/dv_b) (device float32; any
+ * may be NULL but not all).  The velocity sums run in a fixed order.  Uses
+ * the instrument's workspace: calls on one instrument must not overlap.
+ * Enqueue-only; no allocation, so it may be captured in a hipGraph. */
+int pz_inst_backward(const pz_inst* inst, const float* F, const float* Fc, const float* vel, const float* dL_df,
+                     float* dL_dF, float* dL_dFc, float* g_vel, pz_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,11 @@ class pz_options(C.Structure):
                 ("lines_per_chunk", C.c_int32), ("flags", C.c_int32), ("center_eta", C.c_double)]
 
 
+class pz_inst_desc(C.Structure):
+    _fields_ = [("P", C.c_int32), ("lam_obs_nm", _c_double_p), ("lsf_sigma_ln", _c_double_p),
+                ("lsf_trunc", C.c_double), ("vb_max_kms", C.c_double)]
+
+
 class pz_atmos(C.Structure):
     _fields_ = [("D", C.c_int32), ("S", C.c_int32), ("T", C.c_void_p), ("m", C.c_void_p), ("ne", C.c_void_p),
                 ("npert", C.c_void_p), ("rho", C.c_void_p), ("n_species", C.c_void_p),
@@ -116,8 +121,14 @@ def _load():
     lib.pz_autotune.argtypes = [C.POINTER(pz_grid), C.POINTER(pz_lines), C.c_int32, C.c_int32,
                                 C.POINTER(pz_options), C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_int32,
                                 C.POINTER(pz_options), C.POINTER(C.c_float)]
+    lib.pz_inst_create.argtypes = [C.POINTER(pz_grid), C.POINTER(pz_inst_desc), C.POINTER(C.c_void_p)]
+    lib.pz_inst_destroy.argtypes = [C.c_void_p]
+    lib.pz_inst_destroy.restype = None
+    lib.pz_inst_forward.argtypes = [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p]
+    lib.pz_inst_backward.argtypes = [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]
     for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
-                 "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune"):
+                 "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune",
+                 "pz_inst_create", "pz_inst_forward", "pz_inst_backward"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -128,7 +139,8 @@ EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "
            "pz_plan_profile", "pz_plan_profile_read",
            "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_opacity_adjoint",
            "pz_debug_formal_solve",
-           "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune")
+           "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune",
+           "pz_inst_create", "pz_inst_destroy", "pz_inst_forward", "pz_inst_backward")
 
 
 def _check(rc):
@@ -408,3 +420,45 @@ def PzSynth():
     if _PzSynth is None:
         _PzSynth = _autograd_function()
     return _PzSynth
+
+
+# ----------------------------------------------------------------- instrument
+class Instrument:
+    """pz_inst_create / pz_inst_destroy: the instrument operator of Eq. 31 for a
+    synthesis grid, observed pixel centres (nm), LSF widths (ln lambda) and the
+    largest broadening velocity (km/s)."""
+
+    def __init__(self, grid, lam_obs_nm, lsf_sigma_ln, vb_max_kms, lsf_trunc=0.0):
+        import numpy as np
+        self._lam = np.ascontiguousarray(lam_obs_nm, dtype=np.float64)
+        self._sig = np.ascontiguousarray(lsf_sigma_ln, dtype=np.float64)
+        g = pz_grid(float(grid.lam_first_nm), float(grid.R), int(grid.N))
+        d = pz_inst_desc(int(self._lam.size), self._lam.ctypes.data_as(_c_double_p),
+                         self._sig.ctypes.data_as(_c_double_p), float(lsf_trunc), float(vb_max_kms))
+        h = C.c_void_p()
+        _check(lib.pz_inst_create(C.byref(g), C.byref(d), C.byref(h)))
+        self.handle = h
+        self.N, self.P = int(grid.N), int(self._lam.size)
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib.pz_inst_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def pz_inst_forward(inst, F, Fc, vel, KF=None, KFc=None, f=None, stream=None):
+    """f = K S B F / K S B Fc on torch's current stream (device float32 tensors)."""
+    _check(lib.pz_inst_forward(inst.handle, _ptr(F), _ptr(Fc), _ptr(vel), _ptr(KF), _ptr(KFc), _ptr(f),
+                               _stream(stream)))
+
+
+def pz_inst_backward(inst, F, Fc, vel, dL_df, dL_dF=None, dL_dFc=None, g_vel=None, stream=None):
+    """VJP of pz_inst_forward's f for the seed dL_df."""
+    _check(lib.pz_inst_backward(inst.handle, _ptr(F), _ptr(Fc), _ptr(vel), _ptr(dL_df), _ptr(dL_dF),
+                                _ptr(dL_dFc), _ptr(g_vel), _stream(stream)))

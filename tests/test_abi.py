@@ -108,3 +108,33 @@ def test_entry_points_reject_null_before_device_work(pz):
     assert pz.lib.pz_debug_formal_solve(8, 4, None, None, 0, None, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.synth_batch(None, 1, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.pz_plan_info(None, None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("case", ["support_low", "support_high", "order", "sigma", "vbmax", "J", "P"])
+def test_instrument_validation(pz, case):
+    """pz_inst_create validates on the host before any device call."""
+    import numpy as np
+    g = pz.pz_grid(1550.0, 3e5, 1200)
+    h = np.log1p(1.0 / 3e5)
+    lam = 1550.0 * np.exp(h * np.linspace(300, 900, 40))
+    sig = np.full(40, 2e-5)
+    vb, P = 10.0, 40
+    if case == "support_low":
+        lam[0] = 1550.0 * np.exp(h * 3)
+    elif case == "support_high":
+        lam[-1] = 1550.0 * np.exp(h * 1198)
+    elif case == "order":
+        lam[5] = lam[4]
+    elif case == "sigma":
+        sig[3] = 0.0
+    elif case == "vbmax":
+        vb = 0.0
+    elif case == "J":
+        vb = 1e5
+    elif case == "P":
+        P = 0
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    d = pz.pz_inst_desc(P, dp(lam), dp(sig), 0.0, vb)
+    out = C.c_void_p()
+    rc = pz.lib.pz_inst_create(C.byref(g), C.byref(d), C.byref(out))
+    assert rc in (-1, -2) and out.value is None, (rc, pz.lib.pz_last_error())
