@@ -97,12 +97,16 @@ def population_factor(atm, dA):
 
 
 # -------------------------------------------------------------------- line params
-def line_depth_params(atm, lines, dgf, ddamp, dA, xi_kms):
+def line_depth_params(atm, lines, dgf, ddamp, dA, xi_kms, ddamp_family=None):
     """Per (line, depth): Doppler width dnu_D [Hz], damping ratio a and the
     frequency-integrated line strength s (per unit mass), Eqs. 4-5 and 30.
 
     kappa_{l}(nu_i, j) = s_lj * H(a_lj, v) / (sqrt(pi) dnu_D,lj).
-    Returns dict of [L, D] arrays plus the per-line rest frequency.
+    The damping width is 10^ddamp (g_rad 10^d_rad + g_S n_e 10^d_S +
+    g_vdW n_pert 10^d_vdW): Eq. 30 corrects each family; ddamp scales the
+    total (both default to 0).  Returns dict of [L, D] arrays (gam_fam holds
+    the three corrected family widths, [3, L, D]) plus the per-line rest
+    frequency.
     """
     T = atm.T[None, :]
     mass = atm.mass_amu[lines.species][:, None] * AMU
@@ -110,17 +114,19 @@ def line_depth_params(atm, lines, dgf, ddamp, dA, xi_kms):
     dv = np.sqrt(2.0 * K_BOLTZ * T / mass + xi * xi)                  # Eq. 5
     nu_l = C_LIGHT / (lines.lam0_nm * 1.0e-7)
     dnu = nu_l[:, None] * dv / C_LIGHT                                # Eq. 5
-    gamma = (10.0 ** lines.log_grad[:, None]
-             + 10.0 ** lines.log_gstark[:, None] * atm.ne[None, :]
-             + 10.0 ** lines.log_gvdw[:, None] * atm.npert[None, :])
-    gamma = gamma * 10.0 ** np.asarray(ddamp)[:, None]                # Eq. 30
+    fam = np.zeros((3, lines.L)) if ddamp_family is None else np.asarray(ddamp_family, np.float64)
+    scale = 10.0 ** np.asarray(ddamp)[:, None]                        # Eq. 30
+    gam_fam = np.stack([10.0 ** (lines.log_grad + fam[0])[:, None] * np.ones_like(T),
+                        10.0 ** (lines.log_gstark + fam[1])[:, None] * atm.ne[None, :],
+                        10.0 ** (lines.log_gvdw + fam[2])[:, None] * atm.npert[None, :]]) * scale
+    gamma = gam_fam[0] + gam_fam[1] + gam_fam[2]
     a = gamma / (4.0 * math.pi * dnu)                                 # Eq. 5
     P = population_factor(atm, dA)[lines.species, lines.ion, :]      # [L, D]
     gf = 10.0 ** (lines.loggf + np.asarray(dgf))                      # Eq. 30
     boltz = np.exp(-lines.E_eV[:, None] * EV / (K_BOLTZ * T))
     stim = 1.0 - np.exp(-H_PLANCK * nu_l[:, None] / (K_BOLTZ * T))   # at nu_l
     s = LINE_CONST * P * gf[:, None] * boltz * stim                   # Eq. 4
-    return dict(dnu=dnu, a=a, s=s, nu_l=nu_l, dv=dv)
+    return dict(dnu=dnu, a=a, s=s, nu_l=nu_l, dv=dv, gam_fam=gam_fam, gamma=gamma)
 
 
 def voigt(a, v):
@@ -162,7 +168,9 @@ def _pair_terms(wl, params, p_idx, l_idx, pix, want_w=False):
     lines = wl.lines.take(l_idx)
     dgf = np.asarray(params.dgf)[l_idx]
     ddamp = np.asarray(params.ddamp)[l_idx]
-    lp = line_depth_params(wl.atm, lines, dgf, ddamp, params.dA, params.xi_kms)
+    fam = getattr(params, "ddamp_family", None)
+    fam = None if fam is None else np.asarray(fam)[:, l_idx]
+    lp = line_depth_params(wl.atm, lines, dgf, ddamp, params.dA, params.xi_kms, fam)
     nu_i = C_LIGHT / (wavelengths_nm(wl.grid, np.asarray(pix)[p_idx]) * 1.0e-7)
     v = (nu_i[:, None] - lp["nu_l"][:, None]) / lp["dnu"]
     return lp, v
@@ -488,14 +496,17 @@ def line_gradients(wl, params, g, pix, line_subset=None, absolute=False):
     dkappa/d xi    = -K (H + a dH/da + v dH/dv) * d ln dnu / d xi,
                      d ln dnu / d xi = xi / dv^2 (xi in the units of dv)
     with dH/dv = -2 (v H - a L), dH/da = 2 (v L + a H) - 2/sqrt(pi), w = H + i L.
-    Returns (G_gf[L], G_damp[L], G_xi_per_line[L]) over all lines (zero for lines
-    not in line_subset when given).  With absolute=True every term enters with
+    dkappa/d d_beta = ln10 K a dH/da * g_beta / Gamma for damping family beta
+    (its share of the corrected width; the three sum to dkappa/d ddamp).
+    Returns (G_gf[L], G_damp[L], G_xi_per_line[L], G_damp_family[3, L]) over
+    all lines (zero for lines not in line_subset when given).  With absolute=True every term enters with
     its absolute value: sum |g dkappa/dp|, the scale against which the
     rounding error of the sum is measured (its condition).
     """
     pix = np.asarray(pix, np.int64)
     L = wl.lines.L
     Ggf, Gd, Gxi = np.zeros(L), np.zeros(L), np.zeros(L)
+    Gdf = np.zeros((3, L))
     p_idx, l_idx = window_pairs(wl.grid, wl.lines, wl.window_nm, pix)
     if line_subset is not None:
         sel = np.isin(l_idx, np.asarray(line_subset))
@@ -518,12 +529,15 @@ def line_gradients(wl, params, g, pix, line_subset=None, absolute=False):
         t_xi = gij * (-K) * (H + a * Ha + v * Hv) * dlndnu_dxi
         mask = _center_mask(wl, lp, wl.lines.lam0_nm[ll][:, None], v)   # piecewise constant in the parameters
         t_gf, t_d, t_xi = t_gf * mask, t_d * mask, t_xi * mask
+        t_df = t_d[None] * (lp["gam_fam"] / lp["gamma"][None])
         if absolute:
-            t_gf, t_d, t_xi = np.abs(t_gf), np.abs(t_d), np.abs(t_xi)
+            t_gf, t_d, t_xi, t_df = np.abs(t_gf), np.abs(t_d), np.abs(t_xi), np.abs(t_df)
         np.add.at(Ggf, ll, np.sum(t_gf, axis=1))
         np.add.at(Gd, ll, np.sum(t_d, axis=1))
         np.add.at(Gxi, ll, np.sum(t_xi, axis=1))
-    return Ggf, Gd, Gxi
+        for f in range(3):
+            np.add.at(Gdf[f], ll, np.sum(t_df[f], axis=1))
+    return Ggf, Gd, Gxi, Gdf
 
 
 def adjoint(wl, params, dLdF, pix=None, line_subset=None, conditions=False):
@@ -539,15 +553,15 @@ def adjoint(wl, params, dLdF, pix=None, line_subset=None, conditions=False):
     pix = np.arange(wl.grid.N) if pix is None else np.asarray(pix, np.int64)
     kl = line_opacity(wl, params, pix)
     g = opacity_adjoint(wl, kl, np.asarray(dLdF, np.float64), pix)
-    Ggf, Gd, Gxi = line_gradients(wl, params, g, pix, line_subset)
+    Ggf, Gd, Gxi, Gdf = line_gradients(wl, params, g, pix, line_subset)
     GA = np.zeros(wl.atm.S)
     np.add.at(GA, wl.lines.species, Ggf)     # dA_s enters exactly like dgf of its lines
-    out = dict(g_loggf=Ggf, g_damp=Gd, g_abund=GA, g_xi=float(np.sum(Gxi)), g_kappa=g)
+    out = dict(g_loggf=Ggf, g_damp=Gd, g_abund=GA, g_xi=float(np.sum(Gxi)), g_damp_family=Gdf, g_kappa=g)
     if conditions:
-        Agf, Ad, Axi = line_gradients(wl, params, g, pix, line_subset, absolute=True)
+        Agf, Ad, Axi, Adf = line_gradients(wl, params, g, pix, line_subset, absolute=True)
         AA = np.zeros(wl.atm.S)
         np.add.at(AA, wl.lines.species, Agf)
-        out.update(abs_loggf=Agf, abs_damp=Ad, abs_abund=AA, abs_xi=float(np.sum(Axi)))
+        out.update(abs_loggf=Agf, abs_damp=Ad, abs_abund=AA, abs_xi=float(np.sum(Axi)), abs_damp_family=Adf)
     return out
 
 

@@ -97,6 +97,7 @@ class Params:
     ddamp: np.ndarray  # [L] dex (scales the total damping width)
     dA: np.ndarray     # [S] dex
     xi_kms: float
+    ddamp_family: np.ndarray = None   # [3, L] dex per damping family (radiative, Stark, van der Waals), or None
 
 
 @dataclasses.dataclass
