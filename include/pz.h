@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PZ_VERSION 2
+#define PZ_VERSION 3
 #define PZ_MAX_DEPTH 80
 
 #define PZ_OK 0
@@ -62,7 +62,9 @@ extern "C" {
 #define PZ_E_UNSUPPORTED -6   /* a valid request this build does not implement  */
 
 #define PZ_QUAD_GAUSS3 0      /* 3-point Gauss-Legendre in mu on [0, 1] (Eq. 8) */
-#define PZ_QUAD_E2 1          /* F = 2 pi int S E2 dtau (exponential integral)  */
+#define PZ_QUAD_E2 1
+#define PZ_FLAG_DAMPING_FAMILIES 1  /* pz_options.flags: synth_backward writes g_damp as [3][L]
+                                       (radiative, Stark, van der Waals: dL/d ddamp_family) */          /* F = 2 pi int S E2 dtau (exponential integral)  */
 
 #define PZ_MODE_FWD 1
 #define PZ_MODE_FWD_BWD 2
@@ -98,7 +100,7 @@ typedef struct {
     int32_t quadrature;         /* PZ_QUAD_GAUSS3 (default, FP32) or PZ_QUAD_E2 (FP64) */
     int32_t tile_px;            /* opacity tile width in pixels: 0 = autotuned/default */
     int32_t lines_per_chunk;    /* lines staged in LDS per step: 0 = default          */
-    int32_t flags;              /* reserved, must be 0                                 */
+    int32_t flags;              /* PZ_FLAG_* bits; others must be 0                    */
     double center_eta;          /* continuum-referenced centre test (Sec. 2.2, Table 2): 0 = off
                                    (plain windowed sum); eta > 0 keeps a (line, depth) pair only
                                    if K H(a,0) >= eta kappa_c(lambda_l), and a kept pair deposits
@@ -128,13 +130,17 @@ typedef struct {
 } pz_atmos;
 
 /* Corrections of Eq. 30 (device float32 arrays; NULL means all zero).
- * gf' = gf 10^dgf, Gamma' = Gamma 10^ddamp, n_s' = n_s 10^dA.  xi_kms is a
- * device pointer to one float (microturbulence, km/s) and is required. */
+ * gf' = gf 10^dgf, n_s' = n_s 10^dA, and the damping width
+ * Gamma' = 10^ddamp (g_rad 10^d_rad + g_S n_e 10^d_S + g_vdW n_pert 10^d_vdW):
+ * Eq. 30 corrects the three families separately (ddamp_family), ddamp
+ * scales their sum.  xi_kms is a device pointer to one float
+ * (microturbulence, km/s) and is required. */
 typedef struct {
     const float* dgf;           /* [L] caller line order, dex */
     const float* ddamp;         /* [L] caller line order, dex */
     const float* dA;            /* [S] dex                    */
     const float* xi_kms;        /* [1]                        */
+    const float* ddamp_family;  /* [3][L] caller line order, dex: radiative, Stark, van der Waals */
 } pz_params;
 
 /* Library version (PZ_VERSION). */

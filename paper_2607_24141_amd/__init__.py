@@ -27,6 +27,7 @@ PZ_E_NONFINITE = -5
 PZ_E_UNSUPPORTED = -6
 PZ_QUAD_GAUSS3 = 0
 PZ_QUAD_E2 = 1
+PZ_FLAG_DAMPING_FAMILIES = 1
 PZ_MODE_FWD = 1
 PZ_MODE_FWD_BWD = 2
 PZ_MAX_DEPTH = 80
@@ -48,7 +49,7 @@ class pz_lines(C.Structure):
                 ("log_gstark", _c_double_p), ("log_gvdw", _c_double_p)]
 
 
-ABI_VERSION = 2   # PZ_VERSION of include/pz.h the structures below follow
+ABI_VERSION = 3   # PZ_VERSION of include/pz.h the structures below follow
 
 
 class pz_options(C.Structure):
@@ -69,7 +70,8 @@ class pz_atmos(C.Structure):
 
 
 class pz_params(C.Structure):
-    _fields_ = [("dgf", C.c_void_p), ("ddamp", C.c_void_p), ("dA", C.c_void_p), ("xi_kms", C.c_void_p)]
+    _fields_ = [("dgf", C.c_void_p), ("ddamp", C.c_void_p), ("dA", C.c_void_p), ("xi_kms", C.c_void_p),
+                ("ddamp_family", C.c_void_p)]
 
 
 class pz_star(C.Structure):
@@ -308,18 +310,20 @@ class Atmos:
 
 
 class Params:
-    """Device float32 corrections (dgf[L], ddamp[L], dA[S], xi[1]) and pz_params."""
+    """Device float32 corrections (dgf[L], ddamp[L], dA[S], xi[1], optional
+    ddamp_family[3][L]) and pz_params."""
 
-    def __init__(self, dgf, ddamp, dA, xi):
-        self.dgf, self.ddamp, self.dA, self.xi = dgf, ddamp, dA, xi
-        self.c = pz_params(None if dgf is None else dgf.data_ptr(), None if ddamp is None else ddamp.data_ptr(),
-                           None if dA is None else dA.data_ptr(), xi.data_ptr())
+    def __init__(self, dgf, ddamp, dA, xi, ddamp_family=None):
+        self.dgf, self.ddamp, self.dA, self.xi, self.ddamp_family = dgf, ddamp, dA, xi, ddamp_family
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self.c = pz_params(ptr(dgf), ptr(ddamp), ptr(dA), xi.data_ptr(), ptr(ddamp_family))
 
     @classmethod
     def from_host(cls, p, device="cuda"):
         import torch
         f = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=device).contiguous()
-        return cls(f(p.dgf), f(p.ddamp), f(p.dA), f([p.xi_kms]))
+        fam = getattr(p, "ddamp_family", None)
+        return cls(f(p.dgf), f(p.ddamp), f(p.dA), f([p.xi_kms]), None if fam is None else f(fam))
 
 
 # ------------------------------------------------------------- entry points

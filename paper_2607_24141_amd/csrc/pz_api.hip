@@ -119,7 +119,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
         return fail(PZ_E_INVALID_ARG, "tile_px must be 0, 32, 64 or 128 (got %d)", opts->tile_px);
     int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 16;
     if (chunk < 1 || chunk > 16) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 16]");
-    if (opts->flags != 0) return fail(PZ_E_INVALID_ARG, "flags must be 0");
+    if (opts->flags & ~PZ_FLAG_DAMPING_FAMILIES) return fail(PZ_E_INVALID_ARG, "unknown bits in flags");
     if (!(opts->center_eta >= 0.0) || !std::isfinite(opts->center_eta))
         return fail(PZ_E_INVALID_ARG, "center_eta must be finite and >= 0");
     const int L = lines->L, N = grid->N, S = n_species, D = n_depth;
@@ -212,7 +212,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
                  o_sdv = take((size_t)S * D * 8), o_lc = take(Ls * 32), o_zmax = take(Ls * D * 4),
                  o_xlim = take(Ls * 4), o_ikc = take(Ls * 8),
                  o_lp = take(Ls * D * 16), o_kap = take((size_t)D * Npad * 4), o_gk = take((size_t)D * Npad * 4),
-                 o_gl = take(Ls * 3 * 4);
+                 o_gl = take(Ls * 5 * 4);
     const int n_rchunk = (int)((Ls + RCHUNK - 1) / RCHUNK);
     const size_t o_part = take((size_t)(S + 1) * n_rchunk * 4);
     const size_t o_seed = take((size_t)Npad * 4);
@@ -282,6 +282,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->xlim = (float*)(base + o_xlim);
     p->inv_kcl = (double*)(base + o_ikc);
     p->center_eta = opts->center_eta;
+    p->families = (opts->flags & PZ_FLAG_DAMPING_FAMILIES) != 0;
     p->lp = (float4*)(base + o_lp);
     p->kappa = (float*)(base + o_kap);
     p->gk = (float*)(base + o_gk);
@@ -460,6 +461,7 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.alpha = atm->alpha;
     s.dgf = par->dgf;
     s.ddamp = par->ddamp;
+    s.ddamp_family = par->ddamp_family;
     s.dA = par->dA;
     s.xi = par->xi_kms;
     s.pop = p->pop;
@@ -470,6 +472,7 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.inv_kcl = p->inv_kcl;
     s.center_eta = p->center_eta;
     s.center = p->center_eta > 0.0;
+    s.fam = p->families;
     s.lp = p->lp;
     s.kappa = p->kappa;
     s.gk = p->gk;

@@ -63,6 +63,7 @@ struct StarDev {
     // corrections (caller device memory; may be null except xi)
     const float* dgf;
     const float* ddamp;
+    const float* ddamp_family;   // [3][L] caller order, or null
     const float* dA;
     const float* xi;
     // outputs
@@ -82,10 +83,11 @@ struct StarDev {
     double* inv_kcl;             // [L] centre test: 1 / kappa_c at the line centre
     double center_eta;           // centre-test threshold (0: plain windowed sum)
     bool center;
+    bool fam;                    // backward writes per-family damping gradients [3][L]
     float4* lp;                  // [L][D] (c/dv, a^2, K, K a)
     float* kappa;                // [D][Npad]
     float* gk;                   // [D][Npad] dL/dkappa_line
-    float* gline;                // [3][L] per-line sums (sorted order)
+    float* gline;                // [5][L] per-line sums (sorted order): gf, damping (or radiative), xi, Stark, vdW
     float* partial;              // [S+1][n_rchunk] reduction partials
     int n_rchunk;
     const int* tile_order;       // opacity work queue (decreasing cost)
@@ -130,6 +132,7 @@ struct pz_plan {
     float* xlim;
     double* inv_kcl;
     double center_eta;
+    bool families;
     float4* lp;
     float* kappa;
     float* gk;

@@ -48,7 +48,7 @@ __device__ __forceinline__ void dev_populations(const StarDev& s, int idx) {
 // ------------------------------------------------------ line-depth params
 // Per line (Eqs. 4, 5, 30), in float64:
 //   x = (pi e^2/m_e c) 10^(loggf+dgf) lambda_l / sqrt(pi)
-//   y, z, w = 10^ddamp lambda_l / (4 pi) x (g_rad, g_S, g_vdW)
+//   y, z, w = 10^ddamp lambda_l / (4 pi) x (g_rad 10^d_rad, g_S 10^d_S, g_vdW 10^d_vdW)
 __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
     if (l >= s.L) return;
     const int caller = s.ln.perm[l];
@@ -56,8 +56,11 @@ __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
     const double loggf = s.ln.loggf[l] + (s.dgf ? (double)s.dgf[caller] : 0.0);
     const double line_const = PI * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT);
     const double damp = (s.ddamp ? exp10((double)s.ddamp[caller]) : 1.0) * lam / (4.0 * PI);
-    s.lc[l] = make_double4(line_const * exp10(loggf) * lam / sqrt(PI), damp * exp10(s.ln.lgr[l]),
-                           damp * exp10(s.ln.lgs[l]), damp * exp10(s.ln.lgw[l]));
+    const float* df = s.ddamp_family;                    // per-family corrections, [3][L] caller order
+    s.lc[l] = make_double4(line_const * exp10(loggf) * lam / sqrt(PI),
+                           damp * exp10(s.ln.lgr[l] + (df ? (double)df[caller] : 0.0)),
+                           damp * exp10(s.ln.lgs[l] + (df ? (double)df[s.L + caller] : 0.0)),
+                           damp * exp10(s.ln.lgw[l] + (df ? (double)df[2 * s.L + caller] : 0.0)));
     if (s.center) {
         s.xlim[l] = 0.0f;                                // raised by dev_line_params
         s.inv_kcl[l] = 1.0 / (s.kappa0 * pow(lam * 1.0e7 / s.lam_ref_nm, s.alpha));   // 1 / kappa_c(lambda_l)
@@ -730,7 +733,9 @@ __device__ __forceinline__ float wave_sum(float x) {
 
 // One call per wavefront; l must be wavefront-uniform; pw holds the H and L
 // core tables (LDS).
-template <bool CT>
+// FAM: the damping term is split over the three families by their share of
+// the width at each depth, w_beta = Gamma_beta / Gamma.
+template <bool CT, bool FAM>
 __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, const float4* pw) {
     constexpr int WPX = 8, NDG = 8, DPT = (MAXD + NDG - 1) / NDG;
     const int px = lane % WPX, dg = lane / WPX;
@@ -753,7 +758,14 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
         }
     }
     const float xi_f = s.xi[0] * (float)(1.0e10 / (C_LIGHT * C_LIGHT));
-    float sgf = 0.0f, sd = 0.0f, sxi = 0.0f;
+    float gr = 0.0f, gs = 0.0f, gw = 0.0f;
+    if (FAM) {
+        const double4 c = s.lc[l];
+        gr = (float)c.y;
+        gs = (float)c.z;
+        gw = (float)c.w;
+    }
+    float sgf = 0.0f, sd = 0.0f, sxi = 0.0f, sds = 0.0f, sdw = 0.0f;
     for (int p0 = ilo; p0 <= ihi; p0 += WPX) {
         const int i = p0 + px;
         if (i <= ihi) {
@@ -770,8 +782,16 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
                     float KH, KaHa, KX;
                     voigt_KHD(q.y, q.z, q.w, v, v * v, pw, KH, KaHa, KX);
                     sgf = fmaf(gj, KH, sgf);
-                    sd = fmaf(gj, KaHa, sd);
                     sxi = fmaf(-gj * KX, xi_f * q.x * q.x, sxi);
+                    if (FAM) {
+                        const float Gs = gs * (float)s.ne[j], Gw = gw * (float)s.npert[j];
+                        const float t = gj * KaHa / (gr + Gs + Gw);
+                        sd = fmaf(t, gr, sd);
+                        sds = fmaf(t, Gs, sds);
+                        sdw = fmaf(t, Gw, sdw);
+                    } else {
+                        sd = fmaf(gj, KaHa, sd);
+                    }
                 }
             }
         }
@@ -779,19 +799,34 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
     sgf = wave_sum(sgf);
     sd = wave_sum(sd);
     sxi = wave_sum(sxi);
+    if (FAM) {
+        sds = wave_sum(sds);
+        sdw = wave_sum(sdw);
+    }
     if (lane == 0) {
         s.gline[l] = (float)LN10 * sgf;
         s.gline[s.L + l] = (float)LN10 * sd;
         s.gline[2 * s.L + l] = sxi;
+        if (FAM) {
+            s.gline[3 * s.L + l] = (float)LN10 * sds;
+            s.gline[4 * s.L + l] = (float)LN10 * sdw;
+        }
     }
 }
 
 __device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, const float4* pw) {
     if (l >= s.L) return;
-    if (s.center)
-        gather_body<true>(s, l, lane, pw);
-    else
-        gather_body<false>(s, l, lane, pw);
+    if (s.fam) {
+        if (s.center)
+            gather_body<true, true>(s, l, lane, pw);
+        else
+            gather_body<false, true>(s, l, lane, pw);
+    } else {
+        if (s.center)
+            gather_body<true, false>(s, l, lane, pw);
+        else
+            gather_body<false, false>(s, l, lane, pw);
+    }
 }
 
 // ----------------------------------------------------------- reductions
@@ -799,7 +834,13 @@ __device__ __forceinline__ void dev_scatter(const StarDev& s, int l) {
     if (l >= s.L) return;
     const int c = s.ln.perm[l];
     if (s.g_loggf) s.g_loggf[c] = s.gline[l];
-    if (s.g_damp) s.g_damp[c] = s.gline[s.L + l];
+    if (s.g_damp) {
+        s.g_damp[c] = s.gline[s.L + l];
+        if (s.fam) {                                      // [3][L]: radiative, Stark, van der Waals
+            s.g_damp[s.L + c] = s.gline[3 * s.L + l];
+            s.g_damp[2 * s.L + c] = s.gline[4 * s.L + l];
+        }
+    }
 }
 
 // Abundance gradient of species b = sum of the dgf gradients of its lines

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(pz):
 
 
 def test_version(pz):
-    assert pz.pz_version() == pz.ABI_VERSION == 2
+    assert pz.pz_version() == pz.ABI_VERSION == 3
 
 
 def _lines(pz, L=3, **over):
@@ -84,7 +84,7 @@ def test_plan_validation(pz, case, code):
     elif case == "tile":
         kw["opts"] = pz.pz_options(0.3, 0, 48, 0, 0)
     elif case == "flags":
-        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 1)
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 2)
     elif case == "eta":
         kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 0, -1e-3)
     elif case == "eta_nan":

@@ -14,9 +14,9 @@ pytestmark = pytest.mark.gpu
 class Star:
     """Device buffers and descriptor of one star."""
 
-    def __init__(self, pz, wl, tile_px=0, target=False, seed=0):
+    def __init__(self, pz, wl, tile_px=0, target=False, seed=0, fam=False):
         self.wl = wl
-        self.plan = pz.plan_for(wl, tile_px=tile_px)
+        self.plan = pz.plan_for(wl, tile_px=tile_px, flags=pz.PZ_FLAG_DAMPING_FAMILIES if fam else 0)
         self.atm = pz.Atmos(wl.atm)
         self.par = pz.Params.from_host(wl.params)
         p = self.plan
@@ -28,7 +28,7 @@ class Star:
         self.y = torch.as_tensor(rng.uniform(0.3, 1.0, p.N).astype(np.float32), device=d) if target else None
         self.sigma = 0.01
         self.loss = torch.full((1,), np.nan, device=d)
-        self.g = [torch.full((p.L,), np.nan, device=d), torch.full((p.L,), np.nan, device=d),
+        self.g = [torch.full((p.L,), np.nan, device=d), torch.full(((3 if fam else 1) * p.L,), np.nan, device=d),
                   torch.full((p.S,), np.nan, device=d), torch.full((1,), np.nan, device=d)]
 
     def descr(self, pz):
@@ -54,14 +54,17 @@ def _stars(pz):
     specs = [dict(seed=41, L=30, N=700, D=72, tile=32), dict(seed=42, L=80, N=1500, D=72, tile=64),
              dict(seed=43, L=10, N=257, D=8, tile=128), dict(seed=44, L=0, N=300, D=72, tile=64),
              dict(seed=45, L=120, N=2500, D=40, tile=64), dict(seed=46, L=55, N=999, D=72, tile=128),
-             dict(seed=47, L=40, N=600, D=72, tile=32, quad="e2"), dict(seed=48, L=70, N=1100, D=72, tile=32, eta=1e-3)]
+             dict(seed=47, L=40, N=600, D=72, tile=32, quad="e2"), dict(seed=48, L=70, N=1100, D=72, tile=32, eta=1e-3),
+             dict(seed=49, L=50, N=800, D=72, tile=32, fam=True)]
     out = []
     for k, sp in enumerate(specs):
         wl = W.tiny(seed=sp["seed"], L=sp["L"], N=sp["N"], D=sp["D"], S=4, n_molecular=1)
         wl.quadrature = sp.get("quad", "gauss3")
         wl.center_eta = sp.get("eta", 0.0)
         wl.params = W.random_params(np.random.default_rng(k), wl.lines.L, wl.atm.S, 1.1 + 0.2 * k)
-        out.append(Star(pz, wl, sp["tile"], target=(k % 2 == 0), seed=k))
+        if sp.get("fam"):
+            wl.params.ddamp_family = np.random.default_rng(k + 100).normal(0.0, 0.2, (3, wl.lines.L))
+        out.append(Star(pz, wl, sp["tile"], target=(k % 2 == 0), seed=k, fam=sp.get("fam", False)))
     return out
 
 
