@@ -6,10 +6,13 @@ resident in HBM, K timed steps between device synchronisations.  A step is
 one whole forward synthesis (populations, line parameters, windowed Voigt
 opacity, depth scan and Gauss-3 flux for both branches).  Extra fields: the
 forward+backward step (chi^2 loss seed and the adjoint for all 4e5 + 20 + 1
-corrections) and the batched launch over 256 stars, the roofline of the
+corrections), the centre test, the instrument operator, the line calibration
+(objective evaluation and L-BFGS updates over 25,147 correction groups of a
+two-star, three-spectrum fit) and the batched launch over 256 stars, the roofline of the
 dominant kernel (opacity) and the FP64 CPU oracle timed on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes fwd,fwdbwd,batch] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                      [--modes fwd,fwdbwd,center,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -101,7 +104,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fwd,fwdbwd,center,instrument,batch")
+    ap.add_argument("--modes", default="fwd,fwdbwd,center,instrument,calibration,batch")
+    ap.add_argument("--cal-updates", type=int, default=40, help="L-BFGS updates of the calibration block")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -237,6 +241,32 @@ def main():
         out["instrument"] = {"observed_pixels": inst.P, "native_pixels": int(F.numel()),
                              "fwd_us_per_flux_pair": ms_if * 1e3, "bwd_us_per_flux_pair": ms_ib * 1e3}
         inst.destroy()
+
+    # ---- line calibration (Sec. 6): two stars, three spectra, shared group corrections, L-BFGS
+    if "calibration" in modes:
+        from paper_2607_24141_amd import calibrate as CAL
+        log("calibration workload")
+        cw = W.calibration()
+        t0 = time.perf_counter()
+        q, G = pz.correction_groups(cw.lines, W.CAL_DE_CM, W.CAL_DLAM_NM, active=cw.active)
+        t_group = time.perf_counter() - t0
+        gc = CAL.Calibration(cw, groups=(q, G))
+        truth = W.calibration_truth(np.random.default_rng(11), G)
+        cal_sigma = 2e-3
+        gc.set_observed(CAL.mock_observed(gc, truth, cal_sigma, seed=12))
+        theta0 = torch.zeros(4, G, device=dev)
+        ms_eval, _ = timed(lambda: gc.evaluate(theta0), args.steps, args.warmup, torch)
+        log("calibration: %d groups, %.2f ms per evaluation; L-BFGS" % (G, ms_eval))
+        r = CAL.fit(gc, max_iter=args.cal_updates)
+        out["calibration"] = {
+            "workload": cw.name, "records": int(cw.active.sum()), "lines": int(cw.lines.L), "groups": int(G),
+            "corrections": 4 * int(G), "spectra": len(gc.epochs), "syntheses_per_eval": len(gc.stars),
+            "grouping_ms": t_group * 1e3, "ms_per_eval": ms_eval,
+            "lbfgs": {"updates": r["iters"], "evals": r["evals"], "seconds": r["seconds"],
+                      "ms_per_update": r["seconds"] * 1e3 / max(r["iters"], 1), "loss0": r["loss0"],
+                      "loss": r["loss"], "noise_floor": cal_sigma ** 2,
+                      "excess_loss_ratio": (r["loss"] - cal_sigma ** 2) / (r["loss0"] - cal_sigma ** 2)}}
+        del gc
 
     # ---- batched forward + backward over many stars (one captured graph)
     if "batch" in modes:

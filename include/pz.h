@@ -62,9 +62,9 @@ extern "C" {
 #define PZ_E_UNSUPPORTED -6   /* a valid request this build does not implement  */
 
 #define PZ_QUAD_GAUSS3 0      /* 3-point Gauss-Legendre in mu on [0, 1] (Eq. 8) */
-#define PZ_QUAD_E2 1
+#define PZ_QUAD_E2 1          /* F = 2 pi int S E2 dtau (exponential integral)  */
 #define PZ_FLAG_DAMPING_FAMILIES 1  /* pz_options.flags: synth_backward writes g_damp as [3][L]
-                                       (radiative, Stark, van der Waals: dL/d ddamp_family) */          /* F = 2 pi int S E2 dtau (exponential integral)  */
+                                       (radiative, Stark, van der Waals: dL/d ddamp_family) */
 
 #define PZ_MODE_FWD 1
 #define PZ_MODE_FWD_BWD 2
@@ -325,6 +325,76 @@ int pz_inst_forward(const pz_inst* inst, const float* F, const float* Fc, const 
  * Enqueue-only; no allocation, so it may be captured in a hipGraph. */
 int pz_inst_backward(const pz_inst* inst, const float* F, const float* Fc, const float* vel, const float* dL_df,
                      float* dL_dF, float* dL_dFc, float* g_vel, pz_stream stream);
+
+/* ------------------------------------------------------- line calibration
+ * Sec. 6 fits four logarithmic corrections per group of catalogue lines
+ * (Eq. 30: log gf and the radiative, Stark and van der Waals damping
+ * constants) to standard spectra; all lines of a group share its four values.
+ * The calls below build the groups, expand group values to lines, gather
+ * per-line gradients back into groups, and seed the weighted mean-square
+ * objective on the observed pixels of one standard. */
+
+/* Greedy correction groups (host arrays, host code, no device use).  Anchor
+ * complexes come first: lines with anchor[l] >= 0 form one group per distinct
+ * id (ascending id).  Then the remaining calibrated lines are visited by
+ * decreasing loggf (ties: lower index first); each line not yet grouped seeds
+ * a new group holding itself and every ungrouped calibrated line of the same
+ * species and ion with |E - E_seed| <= dE_eV and |lambda0 - lambda0_seed| <=
+ * dlam_nm (float64, both inclusive; measured from the seed, not chained).
+ *   L                  lines (>= 0)
+ *   lam0_nm, E_eV,     [L] line wavelength (nm), lower level energy (eV),
+ *   species, ion,      species index, ionisation stage, log gf
+ *   loggf
+ *   active             [L] or NULL (all): nonzero marks a calibrated line;
+ *                      other lines get group -1
+ *   anchor             [L] or NULL: anchor complex id, or -1
+ *   dE_eV, dlam_nm     tolerances (finite, >= 0); 2.0 cm^-1 = 2.4797e-4 eV
+ *   group_of_line      [L] out: group index, or -1
+ *   n_groups           out: number of groups G
+ * Errors: PZ_E_INVALID_ARG, PZ_E_SHAPE, PZ_E_NONFINITE (non-finite values of
+ * a calibrated line). */
+int pz_correction_groups(int32_t L, const double* lam0_nm, const double* E_eV, const int32_t* species,
+                         const int32_t* ion, const double* loggf, const uint8_t* active, const int32_t* anchor,
+                         double dE_eV, double dlam_nm, int32_t* group_of_line, int32_t* n_groups);
+
+typedef struct pz_groups pz_groups; /* opaque: a group map on the device */
+
+/* Upload a group map: group_of_line [L] (host) with entries in [-1, G)
+ * (-1: the line has no group).  Members of each group are kept in ascending
+ * line order.  Synchronises.  Errors: PZ_E_SHAPE (L or G < 1),
+ * PZ_E_INVALID_ARG (an entry out of range), PZ_E_NOMEM, PZ_E_HIP. */
+int pz_groups_create(int32_t L, int32_t G, const int32_t* group_of_line, pz_groups** out);
+
+/* Release a group map (NULL is a no-op).  Synchronises the device. */
+void pz_groups_destroy(pz_groups* groups);
+
+/* Sizes of a group map. */
+int pz_groups_info(const pz_groups* groups, int32_t* L, int32_t* G);
+
+/* x_line[r][l] = x_group[r][group_of_line[l]], or 0 for a line without a
+ * group, for rows r < R (1 <= R <= 64).  Device float32: x_group [R][G],
+ * x_line [R][L].  With R = 4 and rows (log gf, radiative, Stark, van der
+ * Waals) this yields pz_params.dgf (row 0) and pz_params.ddamp_family (rows
+ * 1-3).  Enqueue-only. */
+int pz_groups_expand(const pz_groups* groups, int32_t R, const float* x_group, float* x_line, pz_stream stream);
+
+/* The transpose: x_group[r][g] = (accumulate ? x_group[r][g] : 0) + a, where
+ * a is the sum of x_line[r][l] over the lines of group g, added one by one in
+ * ascending line order from 0 (bitwise reproducible).  Device float32, shapes
+ * as above.  With synth_backward under PZ_FLAG_DAMPING_FAMILIES writing g_loggf
+ * and g_damp into rows 0 and 1-3 of one [4][L] array, this gives the gradient
+ * of the group corrections.  Enqueue-only. */
+int pz_groups_reduce(const pz_groups* groups, int32_t R, const float* x_line, float* x_group, int32_t accumulate,
+                     pz_stream stream);
+
+/* Weighted mean-square objective of one standard on its observed pixels
+ * (Sec. 6: telluric weights w), L = c sum_p w_p (f_p - y_p)^2.  f, y: [P]
+ * device float32; w: [P] or NULL (all 1); c: the standard's weight (finite).
+ * Writes dL_df [P] = 2 c w (f - y) (may be NULL) and loss [1] (may be NULL,
+ * not both): loss = c * (fixed-order float32 sum), or added to loss[0] when
+ * accumulate is nonzero.  Enqueue-only. */
+int pz_wmse_seed(int32_t P, const float* f, const float* y, const float* w, double c, float* dL_df, float* loss,
+                 int32_t accumulate, pz_stream stream);
 
 #ifdef __cplusplus
 }

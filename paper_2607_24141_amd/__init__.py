@@ -128,9 +128,20 @@ def _load():
     lib.pz_inst_destroy.restype = None
     lib.pz_inst_forward.argtypes = [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p]
     lib.pz_inst_backward.argtypes = [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]
+    lib.pz_correction_groups.argtypes = [C.c_int32] + [C.c_void_p] * 7 + [C.c_double, C.c_double, C.c_void_p,
+                                                                          _c_int_p]
+    lib.pz_groups_create.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.pz_groups_destroy.argtypes = [C.c_void_p]
+    lib.pz_groups_destroy.restype = None
+    lib.pz_groups_info.argtypes = [C.c_void_p, _c_int_p, _c_int_p]
+    lib.pz_groups_expand.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.pz_groups_reduce.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.pz_wmse_seed.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                                 C.c_void_p, C.c_int32, C.c_void_p]
     for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
                  "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune",
-                 "pz_inst_create", "pz_inst_forward", "pz_inst_backward"):
+                 "pz_inst_create", "pz_inst_forward", "pz_inst_backward", "pz_correction_groups",
+                 "pz_groups_create", "pz_groups_info", "pz_groups_expand", "pz_groups_reduce", "pz_wmse_seed"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -142,7 +153,9 @@ EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "
            "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_opacity_adjoint",
            "pz_debug_formal_solve",
            "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune",
-           "pz_inst_create", "pz_inst_destroy", "pz_inst_forward", "pz_inst_backward")
+           "pz_inst_create", "pz_inst_destroy", "pz_inst_forward", "pz_inst_backward",
+           "pz_correction_groups", "pz_groups_create", "pz_groups_destroy", "pz_groups_info", "pz_groups_expand",
+           "pz_groups_reduce", "pz_wmse_seed")
 
 
 def _check(rc):
@@ -424,6 +437,80 @@ def PzSynth():
     if _PzSynth is None:
         _PzSynth = _autograd_function()
     return _PzSynth
+
+
+# ------------------------------------------------------------ line calibration
+CM1_EV = 1.239841984e-4      # one wavenumber (cm^-1) in eV
+
+
+def correction_groups(lines, dE_cm=2.0, dlam_nm=0.035, active=None, anchor=None):
+    """pz_correction_groups on a line list: (group_of_line [L] int32 numpy, G).
+    dE_cm in cm^-1; active: [L] bool or None (all); anchor: [L] int or None."""
+    L = int(lines.L)
+    keep = [np.ascontiguousarray(lines.lam0_nm, np.float64), np.ascontiguousarray(lines.E_eV, np.float64),
+            np.ascontiguousarray(lines.species, np.int32), np.ascontiguousarray(lines.ion, np.int32),
+            np.ascontiguousarray(lines.loggf, np.float64)]
+    act = None if active is None else np.ascontiguousarray(active, np.uint8)
+    anc = None if anchor is None else np.ascontiguousarray(anchor, np.int32)
+    q = np.empty(L, np.int32)
+    G = C.c_int32()
+    p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+    _check(lib.pz_correction_groups(L, *[p(a) for a in keep], p(act), p(anc), float(dE_cm) * CM1_EV,
+                                    float(dlam_nm), p(q), C.byref(G)))
+    return q, G.value
+
+
+class Groups:
+    """pz_groups_create / pz_groups_destroy: a group map on the device, with
+    expand (group values -> lines) and reduce (line values -> group sums)."""
+
+    def __init__(self, group_of_line, G):
+        self._q = np.ascontiguousarray(group_of_line, np.int32)
+        h = C.c_void_p()
+        _check(lib.pz_groups_create(int(self._q.size), int(G), self._q.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.handle = h
+        self.L, self.G = int(self._q.size), int(G)
+
+    def _rows(self, x_group, x_line):
+        R = x_group.numel() // self.G
+        for t in (x_group, x_line):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4 and t.is_contiguous()):
+                raise ValueError("group and line arrays must be contiguous float32 device tensors")
+        if x_group.numel() != R * self.G or x_line.numel() != R * self.L:
+            raise ValueError("shapes: x_group needs R*G = %d*%d and x_line R*L = %d*%d elements (got %d, %d)"
+                             % (R, self.G, R, self.L, x_group.numel(), x_line.numel()))
+        return R
+
+    def expand(self, x_group, x_line, stream=None):
+        """x_line [R][L] from x_group [R][G] (device float32)."""
+        R = self._rows(x_group, x_line)
+        _check(lib.pz_groups_expand(self.handle, int(R), _ptr(x_group), _ptr(x_line), _stream(stream)))
+
+    def reduce(self, x_line, x_group, accumulate=False, stream=None):
+        """x_group [R][G] (+)= fixed-order group sums of x_line [R][L] (device float32)."""
+        R = self._rows(x_group, x_line)
+        _check(lib.pz_groups_reduce(self.handle, int(R), _ptr(x_line), _ptr(x_group), 1 if accumulate else 0,
+                                    _stream(stream)))
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib.pz_groups_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def pz_wmse_seed(f, y, w, c, dL_df=None, loss=None, accumulate=False, stream=None):
+    """dL_df = 2 c w (f - y) and loss (+)= c sum w (f - y)^2 (device float32; w may be None)."""
+    P = f.numel()
+    if y.numel() != P or (w is not None and w.numel() != P) or (dL_df is not None and dL_df.numel() != P):
+        raise ValueError("f, y, w and dL_df must all have P = %d elements" % P)
+    _check(lib.pz_wmse_seed(int(f.numel()), _ptr(f), _ptr(y), _ptr(w), float(c), _ptr(dL_df), _ptr(loss),
+                            1 if accumulate else 0, _stream(stream)))
 
 
 # ----------------------------------------------------------------- instrument

@@ -1,0 +1,105 @@
+"""Host side of the line calibration (Sec. 6): pz_correction_groups, the
+library's greedy grouping, is bit-exact against the oracle's on random
+catalogues (ties in strength, anchors, lines outside the calibration set,
+exact duplicates, zero and unbounded tolerances) and on the full 1500-1700 nm
+calibration catalogue; the group map and loss-seed entry points reject bad
+arguments on the host before any device work (no GPU)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import calibration as OC
+
+
+@pytest.fixture(scope="module")
+def pz():
+    import paper_2607_24141_amd as pz
+    return pz
+
+
+def _oracle(lines, dE_cm, dlam, active=None, anchor=None):
+    return OC.correction_groups(lines.lam0_nm, lines.E_eV, lines.species, lines.ion, lines.loggf,
+                                dE_cm * OC.CM1_EV, dlam, active=active, anchor=anchor)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_groups_match_oracle_random(pz, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lines, _ = W.complex_lines(rng, 3000, 1500.0, 1506.0, 4)
+    lines.loggf = np.round(lines.loggf, 1)                      # ties in strength
+    dup = rng.choice(lines.L, 50, replace=False)                # exact duplicates
+    lines = W.concat_lines(lines, lines.take(dup))
+    active = rng.uniform(size=lines.L) > 0.1
+    anchor = np.full(lines.L, -1, np.int32)
+    anchor[rng.choice(lines.L, 30, replace=False)] = rng.integers(0, 8, 30)
+    for dE, dlam, act, anc in ((2.0, 0.035, None, None), (2.0, 0.035, active, anchor), (0.0, 0.0, active, None),
+                               (np.inf, np.inf, None, None), (5.0, 0.1, None, anchor)):
+        q_ref, G_ref = _oracle(lines, dE, dlam, act, anc)
+        if not np.isfinite(dE):
+            dE_c, dlam_c = 1e300 / OC.CM1_EV, 1e300       # the library requires finite tolerances
+        else:
+            dE_c, dlam_c = dE, dlam
+        q, G = pz.correction_groups(lines, dE_c, dlam_c, active=act, anchor=anc)
+        assert G == G_ref
+        np.testing.assert_array_equal(q, q_ref)
+
+
+def test_groups_match_oracle_full_catalogue(pz):
+    cal = W.calibration()
+    q, G = pz.correction_groups(cal.lines, W.CAL_DE_CM, W.CAL_DLAM_NM, active=cal.active)
+    q_ref, G_ref = _oracle(cal.lines, W.CAL_DE_CM, W.CAL_DLAM_NM, cal.active)
+    assert G == G_ref == 25_147
+    np.testing.assert_array_equal(q, q_ref)
+    assert np.all(q[~cal.active] == -1) and np.all(q[cal.active] >= 0)
+
+
+def test_groups_empty_catalogue(pz):
+    G = C.c_int32(-5)
+    assert pz.lib.pz_correction_groups(0, None, None, None, None, None, None, None, 1.0, 1.0, None,
+                                       C.byref(G)) == pz.PZ_OK
+    assert G.value == 0
+
+
+@pytest.mark.parametrize("case", ["tol", "nan", "null", "L"])
+def test_groups_validation(pz, case):
+    L = 3
+    lam = np.array([1500.0, 1500.01, 1500.02])
+    E = np.zeros(3)
+    gf = np.zeros(3)
+    sp = np.zeros(3, np.int32)
+    q = np.empty(3, np.int32)
+    dE, dlam = 1e-4, 0.035
+    if case == "tol":
+        dlam = -1.0
+    elif case == "nan":
+        gf[1] = np.nan
+    elif case == "L":
+        L = -1
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    G = C.c_int32()
+    rc = pz.lib.pz_correction_groups(L, p(lam), p(E), p(sp), None if case == "null" else p(sp), p(gf), None,
+                                     None, dE, dlam, p(q), C.byref(G))
+    assert rc in (pz.PZ_E_INVALID_ARG, pz.PZ_E_SHAPE, pz.PZ_E_NONFINITE), rc
+    # a non-finite value on a line outside the calibration set is allowed
+    if case == "nan":
+        act = np.array([1, 0, 1], np.uint8)
+        assert pz.lib.pz_correction_groups(3, p(lam), p(E), p(sp), p(sp), p(gf), p(act), None, dE, dlam, p(q),
+                                           C.byref(G)) == pz.PZ_OK
+        assert G.value == 1 and list(q) == [0, -1, 0]
+
+
+def test_group_map_validation(pz):
+    bad = np.array([0, 2, -2], np.int32)
+    out = C.c_void_p()
+    assert pz.lib.pz_groups_create(3, 2, bad.ctypes.data_as(C.c_void_p), C.byref(out)) == pz.PZ_E_INVALID_ARG
+    assert out.value is None
+    assert pz.lib.pz_groups_create(0, 2, bad.ctypes.data_as(C.c_void_p), C.byref(out)) == pz.PZ_E_SHAPE
+    assert pz.lib.pz_groups_create(3, 2, None, C.byref(out)) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_groups_expand(None, 4, None, None, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_groups_reduce(None, 4, None, None, 0, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_groups_info(None, None, None) == pz.PZ_E_INVALID_ARG
+    pz.lib.pz_groups_destroy(None)
+    assert pz.lib.pz_wmse_seed(0, None, None, None, 1.0, None, None, 0, None) == pz.PZ_E_SHAPE
+    assert pz.lib.pz_wmse_seed(5, None, None, None, 1.0, None, None, 0, None) == pz.PZ_E_INVALID_ARG

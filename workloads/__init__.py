@@ -322,3 +322,149 @@ def apogee_instrument(grid, R_lsf=(20000.0, 25000.0), vb_max_kms=20.0):
     sigma_ln = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)) * R)
     assert lam[0] > lo and lam[-1] < hi
     return lam, sigma_ln, vb_max_kms
+
+
+# ------------------------------------------------------------ line calibration
+CM1_EV = 1.239841984e-4        # one wavenumber (cm^-1) in eV
+CAL_RECORDS = 42_886           # atomic records of the 1500-1700 nm calibration interval
+CAL_DE_CM = 2.0                # grouping tolerance in lower-level energy, cm^-1
+CAL_DLAM_NM = 0.035            # grouping tolerance in wavelength, nm
+CAL_TRUTH_SIGMA = (0.1, 0.3, 0.3, 0.2)   # dex: log gf, radiative, Stark, van der Waals
+
+
+def complex_lines(rng, n, lam_lo, lam_hi, n_species, mean_extra=0.7, dlam_nm=0.012, dE_cm=0.7):
+    """n atomic records arranged in complexes (stand-ins for fine-structure,
+    hyperfine and isotopic components): a complex has 1 + Poisson(mean_extra)
+    components sharing its species and ion stage, each within +-dlam_nm of the
+    complex wavelength and +-dE_cm of its lower-level energy, with log gf =
+    complex value + N(0, 0.3).  Complex wavelength, energy, log gf, species and
+    ion follow the atomic recipe.  Returns (LineList, complex id per record)."""
+    est = int(n / (1.0 + mean_extra) * 1.3) + 16
+    ks = 1 + rng.poisson(mean_extra, est)
+    cs = np.cumsum(ks)
+    nc = int(np.searchsorted(cs, n)) + 1
+    ks = ks[:nc].copy()
+    ks[-1] -= int(cs[nc - 1] - n)
+    cid = np.repeat(np.arange(nc), ks)
+    lam_c = rng.uniform(lam_lo, lam_hi, nc)
+    E_c = rng.uniform(0.0, 6.0, nc)
+    gf_c = rng.uniform(-4.0, 0.0, nc)
+    sp_c = rng.integers(0, n_species, nc).astype(np.int32)
+    ion_c = rng.integers(0, 2, nc).astype(np.int32)
+    lam = lam_c[cid] + rng.uniform(-dlam_nm, dlam_nm, n)
+    E = np.maximum(E_c[cid] + rng.uniform(-dE_cm, dE_cm, n) * CM1_EV, 0.0)
+    loggf = gf_c[cid] + rng.normal(0.0, 0.3, n)
+    gr, gs, gw = _damping(rng, n)
+    return LineList(lam, loggf, E, sp_c[cid], ion_c[cid], gr, gs, gw), cid
+
+
+def telluric_weights(rng, lam_nm, n_features, mask_below=0.5):
+    """Relative pixel weights from a synthetic telluric transmission:
+    T = exp(-sum_k d_k exp(-((lambda - lambda_k) / w_k)^2 / 2)) with
+    d_k ~ U[0.02, 1.5], w_k ~ U[0.005, 0.03] nm; weight T where T >= mask_below,
+    else 0 (masked)."""
+    lam_nm = np.asarray(lam_nm, np.float64)
+    tau = np.zeros(lam_nm.size)
+    c = rng.uniform(lam_nm[0], lam_nm[-1], n_features)
+    d = rng.uniform(0.02, 1.5, n_features)
+    w = rng.uniform(0.005, 0.03, n_features)
+    for ck, dk, wk in zip(c, d, w):
+        a, b = np.searchsorted(lam_nm, [ck - 6.0 * wk, ck + 6.0 * wk])
+        tau[a:b] += dk * np.exp(-0.5 * ((lam_nm[a:b] - ck) / wk) ** 2)
+    T = np.exp(-tau)
+    return np.where(T >= mask_below, T, 0.0)
+
+
+def _atlas_pixels(grid, step_px, margin_px, R_atlas):
+    """Observed pixels every step_px native pixels, margin_px in from the grid
+    ends, with a Gaussian LSF of resolving power R_atlas (an FTS-like atlas)."""
+    h = math.log1p(1.0 / grid.R)
+    x0 = math.log(grid.lam_first_nm)
+    x = x0 + h * np.arange(margin_px, grid.N - 1 - margin_px, step_px)
+    sigma = np.full(x.size, 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)) * R_atlas))
+    return np.exp(x), sigma
+
+
+@dataclasses.dataclass
+class CalStandard:
+    """One standard spectrum of the calibration: its workload (shared grid and
+    line list), observed pixels, LSF widths, velocities, weights w and c."""
+    name: str
+    wl: Workload
+    lam_obs_nm: np.ndarray
+    lsf_sigma_ln: np.ndarray
+    vb_max_kms: float
+    vel: tuple
+    w: np.ndarray
+    c: float
+
+
+@dataclasses.dataclass
+class CalWorkload:
+    name: str
+    grid: Grid
+    lines: LineList
+    active: np.ndarray            # [L] bool: atomic records that are calibrated
+    complex_id: np.ndarray        # [n_records] complex of each atomic record
+    standards: list
+
+
+# (name, Teff, log g, [M/H], xi km/s, Gaussian dispersion km/s, epochs): Sec. 6
+CAL_STARS = (("sun", 5777.0, 4.44, 0.0, 0.7, 1.55, 1), ("arcturus", 4286.0, 1.66, -0.52, 1.7, 2.5, 2))
+
+
+def _cal_standards(rng, grid, lines, S, D, species_seed, steps, R_atlas, margin, n_tell):
+    lam_ref = math.sqrt(grid.lam_first_nm * grid_last(grid))
+    out = []
+    for (name, Teff, logg, feh, xi, vb, n_ep), step in zip(CAL_STARS, steps):
+        atm = make_atmosphere(np.random.Generator(np.random.PCG64(species_seed)), Teff, logg, S, n_molecular=2,
+                              metal_shift=feh, lam_ref_nm=lam_ref, D=D)
+        wl = Workload("calibration_%s" % name, grid, atm, lines, zero_params(lines.L, S, xi))
+        lam, sig = _atlas_pixels(grid, step, margin, R_atlas)
+        for e in range(n_ep):
+            w = telluric_weights(rng, lam, n_tell)
+            out.append(CalStandard("%s_%d" % (name, e), wl, lam, sig, 3.0, (0.0, vb), w,
+                                   1.0 / (len(CAL_STARS) * n_ep * float(np.sum(w)))))
+    return out
+
+
+def calibration(seed=240_006, n_records=CAL_RECORDS, n_bands=30):
+    """The line-calibration workload of Sec. 6 on synthetic inputs: 1500-1700 nm
+    at R = 300,000; 42,886 atomic records in complexes (18 species, neutral and
+    singly ionised; calibrated) plus 18,000 molecular band lines (2 species;
+    held fixed); a solar standard (5777 K, log g 4.44, xi 0.7 km/s, Gaussian
+    dispersion 1.55 km/s) and an Arcturus-like giant (4286 K, log g 1.66,
+    [M/H] -0.52, xi 1.7 km/s, 2.5 km/s) observed at two epochs.  Both stars
+    share species properties (one species seed).  Atlas pixels every 1.5 (sun)
+    and 1.4 (giant) native pixels with a Gaussian LSF of R = 250,000; telluric
+    weights from 600 synthetic features per epoch; c gives each star equal
+    total weight and its epochs equal shares, each a weighted mean square."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = 1500.0, 1700.0
+    grid = grid_for(lo, hi, 3.0e5)
+    atomic, cid = complex_lines(rng, n_records, lo, hi, 18)
+    bands = band_lines(rng, n_bands, 600, lo, hi, [18, 19])
+    lines = concat_lines(atomic, bands)
+    active = np.arange(lines.L) < n_records
+    std = _cal_standards(rng, grid, lines, 20, N_DEPTH, seed + 1, (1.5, 1.4), 2.5e5, 60, 600)
+    return CalWorkload("1500-1700nm_R3e5_calibration_%d" % n_records, grid, lines, active, cid, std)
+
+
+def calibration_tiny(seed=31, n_records=40, N=2500, D=24, lam_lo=1550.0):
+    """A small calibration case with the same structure (n_records atomic records
+    in complexes, a few band lines, the two stars, three spectra) on an
+    N-pixel grid with D depths, for brute-force and oracle comparisons."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = Grid(lam_lo, 3.0e5, N)
+    hi = grid_last(grid)
+    atomic, cid = complex_lines(rng, n_records, lam_lo + 0.2, hi - 0.2, 4)
+    bands = band_lines(rng, 1, 6, lam_lo, hi, [4, 5])
+    lines = concat_lines(atomic, bands)
+    active = np.arange(lines.L) < n_records
+    std = _cal_standards(rng, grid, lines, 6, D, seed + 1, (1.5, 1.4), 2.5e5, 60, 4)
+    return CalWorkload("calibration_tiny_%d" % seed, grid, lines, active, cid, std)
+
+
+def calibration_truth(rng, G):
+    """Group corrections [4][G] drawn N(0, CAL_TRUTH_SIGMA) per row."""
+    return np.stack([rng.normal(0.0, s, G) for s in CAL_TRUTH_SIGMA])
