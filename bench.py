@@ -6,13 +6,14 @@ resident in HBM, K timed steps between device synchronisations.  A step is
 one whole forward synthesis (populations, line parameters, windowed Voigt
 opacity, depth scan and Gauss-3 flux for both branches).  Extra fields: the
 forward+backward step (chi^2 loss seed and the adjoint for all 4e5 + 20 + 1
-corrections), the centre test, the instrument operator, the line calibration
+corrections), the centre test, the line-selection keep test (and the forward
+of its kept subset), the instrument operator, the line calibration
 (objective evaluation and L-BFGS updates over 25,147 correction groups of a
 two-star, three-spectrum fit) and the batched launch over 256 stars, the roofline of the
 dominant kernel (opacity) and the FP64 CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                      [--modes fwd,fwdbwd,center,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
+                      [--modes fwd,fwdbwd,center,select,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -104,7 +105,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fwd,fwdbwd,center,instrument,calibration,batch")
+    ap.add_argument("--modes", default="fwd,fwdbwd,center,select,instrument,calibration,batch")
     ap.add_argument("--cal-updates", type=int, default=40, help="L-BFGS updates of the calibration block")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
@@ -225,6 +226,35 @@ def main():
             out["center_test"].update({"fwd_bwd_spectra_per_s": 1000.0 / ms_cfb, "fwd_bwd_ms": ms_cfb,
                                        "speedup_vs_plain_fwd_bwd": out["fwd_bwd"]["ms_per_step"] / ms_cfb})
         cplan.destroy()
+
+    # ---- the line-selection keep test of Eqs. 17-19, then synthesis of the kept subset
+    if "select" in modes:
+        eta_sel, bin_ln = 1.0e-3, 1.0e-3
+        keep_t = torch.empty(L, dtype=torch.uint8, device=dev)
+        nk = torch.empty(1, dtype=torch.int32, device=dev)
+        ms_sel, _ = timed(lambda: pz.pz_select_lines(plan, atm, par, eta_sel, bin_ln, keep=keep_t, n_keep=nk),
+                          args.steps, args.warmup, torch)
+        keep = keep_t.cpu().numpy().astype(bool)
+        idx = np.flatnonzero(keep)
+        sub = W.Workload(wl.name + "_selected", wl.grid, wl.atm, wl.lines.take(idx),
+                         W.Params(wl.params.dgf[idx], wl.params.ddamp[idx], wl.params.dA, wl.params.xi_kms),
+                         window_nm=wl.window_nm)
+        splan = pz.plan_for(sub, tile_px=plan.tile_px)
+        spar = pz.Params.from_host(sub.params)
+        pz.synth_forward(plan, atm, par, F, Fc)
+        f_full, F_full = (F / Fc).clone(), F.clone()
+        sf = lambda: pz.synth_forward(splan, atm, spar, F, Fc)
+        sf()
+        torch.cuda.synchronize()
+        dmax = float(torch.max(torch.abs(F / Fc - f_full)).item())
+        dF_rel = float(torch.max(torch.abs(F - F_full) / F_full).item())
+        n_diff = int((F != F_full).sum().item())
+        ms_sf, _ = timed(sf, args.steps, args.warmup, torch)
+        out["selection"] = {"eta_sel": eta_sel, "bin_ln": bin_ln, "select_ms": ms_sel, "kept": int(idx.size),
+                            "kept_fraction": idx.size / L, "fwd_ms_selected": ms_sf,
+                            "speedup_vs_full_fwd": ms_fwd / ms_sf, "max_abs_dflux_vs_full": dmax,
+                            "max_rel_dF_vs_full": dF_rel, "pixels_changed": n_diff}
+        splan.destroy()
 
     # ---- the instrument operator of Eq. 31 on APOGEE-like pixels (one flux pair)
     if "instrument" in modes:

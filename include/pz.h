@@ -192,6 +192,27 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
                    float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
                    pz_stream stream);
 
+/* Atmosphere-dependent line-selection keep test (Sec. 3, Eqs. 17-19): for
+ * the plan's catalogue and one atmosphere, decides which lines can reach
+ * eta_sel times the continuum at their centre in some layer.  In float64,
+ * per line l of species s, ion r and frequency bin b:
+ *   bins    width bin_ln in ln lambda from the first grid wavelength; b =
+ *           floor(ln(lambda_l / lambda_first) / bin_ln) clamped to the bins
+ *           covering the grid; nu_b at the bin's centre in ln lambda
+ *   C_jb    = eta_sel kappa_c(nu_b) / (1 - exp(-h nu_b / k T_j))  (sigma_c = 0)
+ *   Q_srb   = max_j (n_{s,r} / U_{s,r})_j / (rho_j (dv_{s,j} / c) C_jb)
+ *   R_l     = C_0 gf_l Q_srb / nu_b,  C_0 = sqrt(pi) e^2 / (m_e c)
+ *   keep    iff R_l >= 1 and R_l exp(-E_l / k T_deepest) >= 1
+ * Populations, Doppler widths and gf include the corrections in par (dA,
+ * xi, dgf), as in synth_forward.  Outputs (device, caller line order, any may
+ * be NULL but not all): keep [L] (1 = keep), R [L] and R_deep [L] = R_l
+ * exp(-E_l/kT_deepest) (float64), n_keep [1] (int32, the number kept).
+ * Rewrites the plan's population workspace (a following synth_backward
+ * recomputes the forward).  Enqueue-only.  Errors: PZ_E_INVALID_ARG (eta_sel
+ * or bin_ln not finite and > 0, more than 2^30 bins, no output). */
+int pz_select_lines(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, double eta_sel, double bin_ln,
+                    uint8_t* keep, double* R, double* R_deep, int32_t* n_keep, pz_stream stream);
+
 /* Loss seed of a chi^2 fit to a normalised spectrum: with f = F / Fc (Eq. 9,
  * identity instrument operator) and L = sum_i ((f_i - y_i) / sigma)^2 (the
  * chi^2 objective of Sec. 5), writes dL/dF[N], dL/dFc[N] and L[1] (device

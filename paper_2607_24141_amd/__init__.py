@@ -128,6 +128,8 @@ def _load():
     lib.pz_inst_destroy.restype = None
     lib.pz_inst_forward.argtypes = [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p]
     lib.pz_inst_backward.argtypes = [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]
+    lib.pz_select_lines.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_double, C.c_double,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.pz_correction_groups.argtypes = [C.c_int32] + [C.c_void_p] * 7 + [C.c_double, C.c_double, C.c_void_p,
                                                                           _c_int_p]
     lib.pz_groups_create.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
@@ -141,7 +143,7 @@ def _load():
     for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
                  "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune",
                  "pz_inst_create", "pz_inst_forward", "pz_inst_backward", "pz_correction_groups",
-                 "pz_groups_create", "pz_groups_info", "pz_groups_expand", "pz_groups_reduce", "pz_wmse_seed"):
+                 "pz_select_lines", "pz_groups_create", "pz_groups_info", "pz_groups_expand", "pz_groups_reduce", "pz_wmse_seed"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -154,7 +156,7 @@ EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "
            "pz_debug_formal_solve",
            "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune",
            "pz_inst_create", "pz_inst_destroy", "pz_inst_forward", "pz_inst_backward",
-           "pz_correction_groups", "pz_groups_create", "pz_groups_destroy", "pz_groups_info", "pz_groups_expand",
+           "pz_select_lines", "pz_correction_groups", "pz_groups_create", "pz_groups_destroy", "pz_groups_info", "pz_groups_expand",
            "pz_groups_reduce", "pz_wmse_seed")
 
 
@@ -437,6 +439,28 @@ def PzSynth():
     if _PzSynth is None:
         _PzSynth = _autograd_function()
     return _PzSynth
+
+
+# ------------------------------------------------------------- line selection
+def pz_select_lines(plan, atm, par, eta_sel=1e-3, bin_ln=1e-3, keep=None, R=None, R_deep=None, n_keep=None,
+                    stream=None):
+    """The keep test of Eqs. 17-19 on the device: keep [L] uint8, R and R_deep [L]
+    float64, n_keep [1] int32 (device tensors, caller line order; any may be None)."""
+    for t, n, sz in ((keep, "keep", 1), (R, "R", 8), (R_deep, "R_deep", 8)):
+        if t is not None and (t.numel() != plan.L or t.element_size() != sz or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous device tensor of L = %d elements of %d bytes" % (n, plan.L, sz))
+    if n_keep is not None and (n_keep.numel() != 1 or n_keep.element_size() != 4):
+        raise ValueError("n_keep must be one int32")
+    _check(lib.pz_select_lines(plan.handle, C.byref(atm.c), C.byref(par.c), float(eta_sel), float(bin_ln),
+                               _ptr(keep), _ptr(R), _ptr(R_deep), _ptr(n_keep), _stream(stream)))
+
+
+def select_lines(plan, atm, par, eta_sel=1e-3, bin_ln=1e-3):
+    """Host keep mask ([L] bool, caller order) of pz_select_lines."""
+    import torch
+    keep = torch.empty(plan.L, dtype=torch.uint8, device="cuda")
+    pz_select_lines(plan, atm, par, eta_sel, bin_ln, keep=keep)
+    return keep.cpu().numpy().astype(bool)
 
 
 # ------------------------------------------------------------ line calibration

@@ -555,6 +555,27 @@ int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par
     return PZ_OK;
 }
 
+int pz_select_lines(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, double eta_sel, double bin_ln,
+                    uint8_t* keep, double* R, double* R_deep, int32_t* n_keep, pz_stream stream) {
+    g_err.clear();
+    if (!plan) return fail(PZ_E_INVALID_ARG, "plan is NULL");
+    int rc = check_atmos(plan, atm);
+    if (rc) return rc;
+    if ((rc = check_params(par))) return rc;
+    if (!(eta_sel > 0.0) || !std::isfinite(eta_sel)) return fail(PZ_E_INVALID_ARG, "eta_sel must be finite and > 0");
+    if (!(bin_ln > 0.0) || !std::isfinite(bin_ln)) return fail(PZ_E_INVALID_ARG, "bin_ln must be finite and > 0");
+    if (!keep && !R && !R_deep && !n_keep) return fail(PZ_E_INVALID_ARG, "no output requested");
+    const double span = plan->h * (plan->N - 1);                        // ln(lambda_last / lambda_first)
+    const double Bd = std::floor(span / bin_ln) + 1.0;
+    if (Bd > (double)(1 << 30)) return fail(PZ_E_INVALID_ARG, "bin_ln gives more than 2^30 bins");
+    StarDev s = make_star(plan, atm, par);
+    hipStream_t st = (hipStream_t)stream;
+    const_cast<pz_plan*>(plan)->ws_valid = false;                       // populations are rewritten
+    PZ_HIP(launch_populations(s, st));
+    PZ_HIP(launch_select(s, eta_sel, bin_ln, (int)Bd, keep, R, R_deep, n_keep, st));
+    return PZ_OK;
+}
+
 int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, const float* dL_dF,
                    const float* dL_dFc, float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
                    pz_stream stream) {

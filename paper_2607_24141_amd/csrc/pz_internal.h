@@ -102,6 +102,8 @@ static constexpr int RCHUNK = 2048;      // lines per reduction partial
 int opacity_grid(int tile_px);   // persistent opacity workgroups for this device
 hipError_t launch_populations(const StarDev& s, hipStream_t st);
 hipError_t launch_line_params(const StarDev& s, hipStream_t st);
+hipError_t launch_select(const StarDev& s, double eta, double bin_ln, int B, unsigned char* keep, double* R,
+                         double* Rd, int* n_keep, hipStream_t st);
 hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st);
 hipError_t launch_flux(const StarDev& s, hipStream_t st);
 hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st);

@@ -39,6 +39,11 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
 
 __global__ void k_reset_queue(int* ctr) { ctr[0] = 0; }
 
+__global__ __launch_bounds__(256) void k_select(StarDev s, double eta, double bin_ln, int B, unsigned char* keep,
+                                                double* R, double* Rd, int* n_keep) {
+    dev_select(s, blockIdx.x * blockDim.x + threadIdx.x, eta, bin_ln, B, keep, R, Rd, n_keep);
+}
+
 int opacity_grid(int tile_px) {
     int dev = 0, n_cu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -138,6 +143,13 @@ __global__ __launch_bounds__(1024) void k_chi2_loss(int N, const float* F, const
 hipError_t launch_populations(const StarDev& s, hipStream_t st) {
     const int n = s.S * s.D;
     k_populations<<<(n + 255) / 256, 256, 0, st>>>(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const StarDev& s, double eta, double bin_ln, int B, unsigned char* keep, double* R,
+                         double* Rd, int* n_keep, hipStream_t st) {
+    if (n_keep) k_reset_queue<<<1, 1, 0, st>>>(n_keep);
+    if (s.L > 0) k_select<<<(s.L + 255) / 256, 256, 0, st>>>(s, eta, bin_ln, B, keep, R, Rd, n_keep);
     return hipGetLastError();
 }
 

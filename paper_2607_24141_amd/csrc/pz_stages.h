@@ -45,6 +45,41 @@ __device__ __forceinline__ void dev_populations(const StarDev& s, int idx) {
     s.sdv[sp * s.D + j] = sqrt(2.0 * K_BOLTZ * T / (s.mass[sp] * AMU_G) + xi * xi);
 }
 
+// ------------------------------------------------- line-selection keep test
+// Per sorted line (Sec. 3, Eqs. 17-19), after dev_populations, in float64:
+//   b     = floor(ln(lambda_l / lambda_first) / bin_ln) clamped to [0, B)
+//   nu_b  = frequency at the bin's centre in ln lambda
+//   C_jb  = eta kappa_c(nu_b) / (1 - exp(-h nu_b / k T_j))            (sigma_c = 0)
+//   Q     = max_j pop_{s,r,j} / ((dv_{s,j} / c) C_jb)                  (pop = n / (rho U))
+//   R_l   = sqrt(pi) e^2 / (m_e c) 10^(loggf + dgf) Q / nu_b
+//   keep  = R_l >= 1 and R_l exp(-E_l / k T_deepest) >= 1
+// Q is taken per line over the line's own (species, ion, bin): the same max
+// over the same terms as a per-bin table, so no table is stored.
+__device__ __forceinline__ void dev_select(const StarDev& s, int l, double eta, double bin_ln, int B,
+                                           unsigned char* keep, double* R_out, double* Rd_out, int* n_keep) {
+    if (l >= s.L) return;
+    const int caller = s.ln.perm[l];
+    const int spion = s.ln.spion[l], sp = spion >> 1;
+    const double bf = floor(log(s.ln.lam_cm[l] * 1.0e7 / s.lam_first_nm) / bin_ln);
+    const double b = fmin(fmax(bf, 0.0), (double)(B - 1));
+    const double lam_b = s.lam_first_nm * exp((b + 0.5) * bin_ln);          // nm
+    const double nu_b = C_LIGHT / (lam_b * 1.0e-7);
+    const double kc = s.kappa0 * pow(lam_b / s.lam_ref_nm, s.alpha);
+    double Q = 0.0;
+    for (int j = 0; j < s.D; ++j) {
+        const double C = eta * kc / (-expm1(-H_PLANCK * nu_b / (K_BOLTZ * s.T[j])));
+        Q = fmax(Q, s.pop[spion * s.D + j] / (s.sdv[sp * s.D + j] / C_LIGHT * C));
+    }
+    const double loggf = s.ln.loggf[l] + (s.dgf ? (double)s.dgf[caller] : 0.0);
+    const double R = sqrt(PI) * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT) * exp10(loggf) * Q / nu_b;
+    const double Rd = R * exp(-s.ln.E_eV[l] * EV_ERG / (K_BOLTZ * s.T[s.D - 1]));
+    const bool k = R >= 1.0 && Rd >= 1.0;
+    if (keep) keep[caller] = k ? 1 : 0;
+    if (R_out) R_out[caller] = R;
+    if (Rd_out) Rd_out[caller] = Rd;
+    if (k && n_keep) atomicAdd(n_keep, 1);
+}
+
 // ------------------------------------------------------ line-depth params
 // Per line (Eqs. 4, 5, 30), in float64:
 //   x = (pi e^2/m_e c) 10^(loggf+dgf) lambda_l / sqrt(pi)

@@ -107,6 +107,7 @@ def test_entry_points_reject_null_before_device_work(pz):
     assert pz.lib.pz_debug_formal_solve(1, 4, None, None, 0, None, None) == pz.PZ_E_SHAPE
     assert pz.lib.pz_debug_formal_solve(8, 4, None, None, 0, None, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.synth_batch(None, 1, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_select_lines(None, None, None, 1e-3, 1e-3, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.pz_plan_info(None, None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
 
 
