@@ -62,6 +62,8 @@ class Atmosphere:
     kappa0: float = 1.0    # cm^2 g^-1
     lam_ref_nm: float = 500.0
     alpha: float = -1.0
+    sigma_c: np.ndarray = None   # [D] continuum scattering per unit mass at lam_ref (None: no scattering)
+    sigma_alpha: float = 0.0     # sigma_c(lambda) = sigma_c (lambda / lam_ref)^sigma_alpha
 
     @property
     def D(self):
