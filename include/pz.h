@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PZ_VERSION 3
+#define PZ_VERSION 4
 #define PZ_MAX_DEPTH 80
 
 #define PZ_OK 0
@@ -65,6 +65,8 @@ extern "C" {
 #define PZ_QUAD_E2 1          /* F = 2 pi int S E2 dtau (exponential integral)  */
 #define PZ_FLAG_DAMPING_FAMILIES 1  /* pz_options.flags: synth_backward writes g_damp as [3][L]
                                        (radiative, Stark, van der Waals: dL/d ddamp_family) */
+#define PZ_FLAG_SCATTERING 2        /* pz_options.flags: allocate the workspace of the transfer with
+                                       continuum scattering (atmospheres with sigma_c != NULL) */
 
 #define PZ_MODE_FWD 1
 #define PZ_MODE_FWD_BWD 2
@@ -108,6 +110,9 @@ typedef struct {
                                    R = K / kappa_c(lambda_l); both decided in float64.  Gradients
                                    treat the mask as constant (it is piecewise constant).  Must be
                                    finite and >= 0. */
+    int32_t scatter_max_iter;   /* scattering: iteration cap of the source-function (and adjoint)
+                                   iteration per pixel; 0 = 500 */
+    double scatter_tol;         /* scattering: stop when max_j |dS_j / S_j| <= tol; 0 = 1e-10 */
 } pz_options;
 
 /* One fixed 1-D atmosphere (device arrays, float64, caller-owned).  Depth
@@ -127,6 +132,12 @@ typedef struct {
     double kappa0;              /* continuum: kappa0 (lambda/lambda_ref)^alpha, cm^2 g^-1 */
     double lam_ref_nm;
     double alpha;
+    const double* sigma_c;      /* [D] or NULL: continuum scattering per unit mass at lambda_ref,
+                                   sigma_c(lambda) = sigma_c (lambda/lambda_ref)^sigma_alpha (Eq. 3).
+                                   Non-NULL: S = eps B + (1 - eps) J (Eq. 6), iterated per pixel to
+                                   its fixed point in float64 (Gauss-3 only; the plan needs
+                                   PZ_FLAG_SCATTERING); NULL: S = B */
+    double sigma_alpha;
 } pz_atmos;
 
 /* Corrections of Eq. 30 (device float32 arrays; NULL means all zero).
@@ -191,6 +202,12 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
                    const float* dL_dF, const float* dL_dFc,
                    float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
                    pz_stream stream);
+
+/* Largest number of iterations any pixel used in the last scattering forward
+ * (total branch, continuum branch) and adjoint solve on this plan: iters[3]
+ * (host).  Synchronises the device.  PZ_E_INVALID_ARG without the
+ * scattering workspace. */
+int pz_scatter_iterations(const pz_plan* plan, int32_t* iters);
 
 /* Atmosphere-dependent line-selection keep test (Sec. 3, Eqs. 17-19): for
  * the plan's catalogue and one atmosphere, decides which lines can reach

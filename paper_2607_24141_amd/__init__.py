@@ -28,6 +28,7 @@ PZ_E_UNSUPPORTED = -6
 PZ_QUAD_GAUSS3 = 0
 PZ_QUAD_E2 = 1
 PZ_FLAG_DAMPING_FAMILIES = 1
+PZ_FLAG_SCATTERING = 2
 PZ_MODE_FWD = 1
 PZ_MODE_FWD_BWD = 2
 PZ_MAX_DEPTH = 80
@@ -49,12 +50,13 @@ class pz_lines(C.Structure):
                 ("log_gstark", _c_double_p), ("log_gvdw", _c_double_p)]
 
 
-ABI_VERSION = 3   # PZ_VERSION of include/pz.h the structures below follow
+ABI_VERSION = 4   # PZ_VERSION of include/pz.h the structures below follow
 
 
 class pz_options(C.Structure):
     _fields_ = [("window_nm", C.c_double), ("quadrature", C.c_int32), ("tile_px", C.c_int32),
-                ("lines_per_chunk", C.c_int32), ("flags", C.c_int32), ("center_eta", C.c_double)]
+                ("lines_per_chunk", C.c_int32), ("flags", C.c_int32), ("center_eta", C.c_double),
+                ("scatter_max_iter", C.c_int32), ("scatter_tol", C.c_double)]
 
 
 class pz_inst_desc(C.Structure):
@@ -66,7 +68,8 @@ class pz_atmos(C.Structure):
     _fields_ = [("D", C.c_int32), ("S", C.c_int32), ("T", C.c_void_p), ("m", C.c_void_p), ("ne", C.c_void_p),
                 ("npert", C.c_void_p), ("rho", C.c_void_p), ("n_species", C.c_void_p),
                 ("chi_ion_eV", C.c_void_p), ("U", C.c_void_p), ("mass_amu", C.c_void_p),
-                ("kappa0", C.c_double), ("lam_ref_nm", C.c_double), ("alpha", C.c_double)]
+                ("kappa0", C.c_double), ("lam_ref_nm", C.c_double), ("alpha", C.c_double),
+                ("sigma_c", C.c_void_p), ("sigma_alpha", C.c_double)]
 
 
 class pz_params(C.Structure):
@@ -128,6 +131,7 @@ def _load():
     lib.pz_inst_destroy.restype = None
     lib.pz_inst_forward.argtypes = [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p]
     lib.pz_inst_backward.argtypes = [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]
+    lib.pz_scatter_iterations.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
     lib.pz_select_lines.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_double, C.c_double,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.pz_correction_groups.argtypes = [C.c_int32] + [C.c_void_p] * 7 + [C.c_double, C.c_double, C.c_void_p,
@@ -143,7 +147,7 @@ def _load():
     for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
                  "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune",
                  "pz_inst_create", "pz_inst_forward", "pz_inst_backward", "pz_correction_groups",
-                 "pz_select_lines", "pz_groups_create", "pz_groups_info", "pz_groups_expand", "pz_groups_reduce", "pz_wmse_seed"):
+                 "pz_select_lines", "pz_scatter_iterations", "pz_groups_create", "pz_groups_info", "pz_groups_expand", "pz_groups_reduce", "pz_wmse_seed"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -156,7 +160,7 @@ EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "
            "pz_debug_formal_solve",
            "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune",
            "pz_inst_create", "pz_inst_destroy", "pz_inst_forward", "pz_inst_backward",
-           "pz_select_lines", "pz_correction_groups", "pz_groups_create", "pz_groups_destroy", "pz_groups_info", "pz_groups_expand",
+           "pz_select_lines", "pz_scatter_iterations", "pz_correction_groups", "pz_groups_create", "pz_groups_destroy", "pz_groups_info", "pz_groups_expand",
            "pz_groups_reduce", "pz_wmse_seed")
 
 
@@ -214,10 +218,10 @@ class Plan:
     """pz_plan_create / pz_plan_destroy around host line arrays (float64)."""
 
     def __init__(self, grid, lines, n_species, n_depth, window_nm=0.3, quadrature=PZ_QUAD_GAUSS3,
-                 tile_px=0, lines_per_chunk=0, flags=0, center_eta=0.0):
+                 tile_px=0, lines_per_chunk=0, flags=0, center_eta=0.0, scatter_max_iter=0, scatter_tol=0.0):
         g, ln, keep = c_grid_lines(grid, lines)
         opts = pz_options(float(window_nm), int(quadrature), int(tile_px), int(lines_per_chunk), int(flags),
-                          float(center_eta))
+                          float(center_eta), int(scatter_max_iter), float(scatter_tol))
         h = C.c_void_p()
         _check(lib.pz_plan_create(C.byref(g), C.byref(ln), int(n_species), int(n_depth), C.byref(opts),
                                   C.byref(h)))
@@ -230,6 +234,13 @@ class Plan:
         ev = C.c_int64()
         _check(lib.pz_plan_info(self.handle, *[C.byref(x) for x in v], C.byref(ev)))
         return tuple(x.value for x in v) + (ev.value,)
+
+    def scatter_iterations(self):
+        """pz_scatter_iterations: the largest iteration counts of the last scattering
+        forward (total, continuum) and adjoint solve."""
+        it = (C.c_int32 * 3)()
+        _check(lib.pz_scatter_iterations(self.handle, it))
+        return tuple(it)
 
     def invalidate(self):
         """pz_plan_invalidate: the next synth_backward recomputes the forward opacity."""
@@ -260,6 +271,8 @@ class Plan:
 
 def plan_for(workload, **kw):
     kw.setdefault("center_eta", getattr(workload, "center_eta", 0.0))
+    if getattr(workload.atm, "sigma_c", None) is not None:
+        kw["flags"] = kw.get("flags", 0) | PZ_FLAG_SCATTERING
     return Plan(workload.grid, workload.lines, workload.atm.S, workload.atm.D,
                 window_nm=workload.window_nm,
                 quadrature=PZ_QUAD_GAUSS3 if workload.quadrature == "gauss3" else PZ_QUAD_E2, **kw)
@@ -321,7 +334,12 @@ class Atmos:
         self.c = pz_atmos(int(atm.T.shape[0]), int(atm.mass_amu.shape[0]), t["T"].data_ptr(), t["m"].data_ptr(),
                           t["ne"].data_ptr(), t["npert"].data_ptr(), t["rho"].data_ptr(),
                           t["n_species"].data_ptr(), t["chi"].data_ptr(), t["U"].data_ptr(),
-                          t["mass"].data_ptr(), float(atm.kappa0), float(atm.lam_ref_nm), float(atm.alpha))
+                          t["mass"].data_ptr(), float(atm.kappa0), float(atm.lam_ref_nm), float(atm.alpha),
+                          None, float(getattr(atm, "sigma_alpha", 0.0)))
+        sig = getattr(atm, "sigma_c", None)
+        if sig is not None:
+            t["sigma_c"] = f(sig)
+            self.c.sigma_c = t["sigma_c"].data_ptr()
 
 
 class Params:

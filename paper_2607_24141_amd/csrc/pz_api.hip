@@ -119,7 +119,14 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
         return fail(PZ_E_INVALID_ARG, "tile_px must be 0, 32, 64 or 128 (got %d)", opts->tile_px);
     int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 16;
     if (chunk < 1 || chunk > 16) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 16]");
-    if (opts->flags & ~PZ_FLAG_DAMPING_FAMILIES) return fail(PZ_E_INVALID_ARG, "unknown bits in flags");
+    if (opts->flags & ~(PZ_FLAG_DAMPING_FAMILIES | PZ_FLAG_SCATTERING))
+        return fail(PZ_E_INVALID_ARG, "unknown bits in flags");
+    if (opts->scatter_max_iter < 0 || opts->scatter_max_iter > 100000)
+        return fail(PZ_E_INVALID_ARG, "scatter_max_iter must be in [0, 100000]");
+    if (!(opts->scatter_tol >= 0.0) || !std::isfinite(opts->scatter_tol))
+        return fail(PZ_E_INVALID_ARG, "scatter_tol must be finite and >= 0");
+    if ((opts->flags & PZ_FLAG_SCATTERING) && opts->quadrature != PZ_QUAD_GAUSS3)
+        return fail(PZ_E_UNSUPPORTED, "scattering is implemented with the Gauss-3 quadrature only");
     if (!(opts->center_eta >= 0.0) || !std::isfinite(opts->center_eta))
         return fail(PZ_E_INVALID_ARG, "center_eta must be finite and >= 0");
     const int L = lines->L, N = grid->N, S = n_species, D = n_depth;
@@ -217,6 +224,9 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     const size_t o_part = take((size_t)(S + 1) * n_rchunk * 4);
     const size_t o_seed = take((size_t)Npad * 4);
     const size_t o_order = take((size_t)n_tiles * 4), o_qctr = take(4);
+    const bool scatter_ws = (opts->flags & PZ_FLAG_SCATTERING) != 0;
+    const size_t o_sc = scatter_ws ? take((size_t)SC_WS_ARRAYS * D * Npad * 8) : 0;
+    const size_t o_sci = scatter_ws ? take((size_t)3 * Npad * 4) : 0;
     // Voigt evaluations per tile (orders the batched opacity work)
     std::vector<int64_t> tcost(n_tiles, 0);
     for (int k = 0; k < L; ++k) {
@@ -283,6 +293,11 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->inv_kcl = (double*)(base + o_ikc);
     p->center_eta = opts->center_eta;
     p->families = (opts->flags & PZ_FLAG_DAMPING_FAMILIES) != 0;
+    p->scatter_ws = scatter_ws;
+    p->sc = scatter_ws ? (double*)(base + o_sc) : nullptr;
+    p->sc_iters = scatter_ws ? (int*)(base + o_sci) : nullptr;
+    p->sc_max_iter = opts->scatter_max_iter ? opts->scatter_max_iter : 500;
+    p->sc_tol = opts->scatter_tol > 0.0 ? opts->scatter_tol : 1e-10;
     p->lp = (float4*)(base + o_lp);
     p->kappa = (float*)(base + o_kap);
     p->gk = (float*)(base + o_gk);
@@ -417,6 +432,11 @@ int check_atmos(const pz_plan* plan, const pz_atmos* atm) {
     if (!std::isfinite(atm->kappa0) || !std::isfinite(atm->lam_ref_nm) || !std::isfinite(atm->alpha) ||
         !(atm->lam_ref_nm > 0.0))
         return fail(PZ_E_NONFINITE, "continuum parameters must be finite (lam_ref_nm > 0)");
+    if (atm->sigma_c) {
+        if (!plan->scatter_ws)
+            return fail(PZ_E_INVALID_ARG, "atmosphere has sigma_c but the plan was built without PZ_FLAG_SCATTERING");
+        if (!std::isfinite(atm->sigma_alpha)) return fail(PZ_E_NONFINITE, "sigma_alpha must be finite");
+    }
     return PZ_OK;
 }
 
@@ -459,6 +479,13 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.kappa0 = atm->kappa0;
     s.lam_ref_nm = atm->lam_ref_nm;
     s.alpha = atm->alpha;
+    s.sigma_c = atm->sigma_c;
+    s.sigma_alpha = atm->sigma_alpha;
+    s.scatter = atm->sigma_c != nullptr;
+    s.sc_max_iter = p->sc_max_iter;
+    s.sc_tol = p->sc_tol;
+    s.sc = p->sc;
+    s.sc_iters = p->sc_iters;
     s.dgf = par->dgf;
     s.ddamp = par->ddamp;
     s.ddamp_family = par->ddamp_family;
@@ -505,6 +532,7 @@ struct StageTimer {
 void record_workspace(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, hipStream_t st) {
     pz_plan* p = const_cast<pz_plan*>(plan);
     p->ws_valid = true;
+    p->sc_ok = false;                    // set by a forward flux stage that solves the scattering
     p->ws_atm = *atm;
     p->ws_par = *par;
     p->ws_stream = st;
@@ -531,9 +559,36 @@ int enqueue_opacity(const pz_plan* p, const StarDev& s, hipStream_t st) {
     return PZ_OK;
 }
 
+// The scattering backward needs the forward's converged source functions: solve
+// them again (no flux output) unless the last forward on this workspace did.
+int ensure_scatter_forward(const pz_plan* p, const StarDev& s, hipStream_t st) {
+    if (!s.scatter || p->sc_ok) return PZ_OK;
+    StarDev f = s;
+    f.F = nullptr;
+    f.Fc = nullptr;
+    PZ_HIP(launch_flux(f, st));
+    const_cast<pz_plan*>(p)->sc_ok = true;
+    return PZ_OK;
+}
+
 }  // namespace pz
 
 extern "C" {
+
+int pz_scatter_iterations(const pz_plan* plan, int32_t* iters) {
+    g_err.clear();
+    if (!plan || !iters) return fail(PZ_E_INVALID_ARG, "plan and iters are required");
+    if (!plan->scatter_ws) return fail(PZ_E_INVALID_ARG, "the plan has no scattering workspace");
+    std::vector<int32_t> h((size_t)3 * plan->Npad);
+    PZ_HIP(hipDeviceSynchronize());
+    PZ_HIP(hipMemcpy(h.data(), plan->sc_iters, h.size() * 4, hipMemcpyDeviceToHost));
+    for (int r = 0; r < 3; ++r) {
+        int32_t mx = 0;
+        for (int i = 0; i < plan->N; ++i) mx = std::max(mx, h[(size_t)r * plan->Npad + i]);
+        iters[r] = mx;
+    }
+    return PZ_OK;
+}
 
 int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, float* F, float* Fc,
                   pz_stream stream) {
@@ -552,6 +607,7 @@ int synth_forward(const pz_plan* plan, const pz_atmos* atm, const pz_params* par
     record_workspace(plan, atm, par, st);
     StageTimer t(plan, PZ_STAGE_FLUX, st);
     PZ_HIP(launch_flux(s, st));
+    const_cast<pz_plan*>(plan)->sc_ok = s.scatter;
     return PZ_OK;
 }
 
@@ -598,6 +654,7 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
         if ((rc = enqueue_opacity(plan, s, st))) return rc;
         record_workspace(plan, atm, par, st);
     }
+    if ((rc = ensure_scatter_forward(plan, s, st))) return rc;
     {
         StageTimer t(plan, PZ_STAGE_REVERSE_SCAN, st);
         PZ_HIP(launch_reverse_scan(s, st));
@@ -627,6 +684,7 @@ int pz_debug_opacity_adjoint(const pz_plan* plan, const pz_atmos* atm, const pz_
         if ((rc = enqueue_opacity(plan, s, st))) return rc;
         record_workspace(plan, atm, par, st);
     }
+    if ((rc = ensure_scatter_forward(plan, s, st))) return rc;
     PZ_HIP(launch_reverse_scan(s, st));
     PZ_HIP(hipMemcpy2DAsync(g_kappa, (size_t)plan->N * 4, plan->gk, (size_t)plan->Npad * 4, (size_t)plan->N * 4,
                             plan->D, hipMemcpyDeviceToDevice, st));

@@ -230,6 +230,8 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
         int rc = check_atmos(st.plan, &st.atm);
         if (rc) return rc;
         if ((rc = check_params(&st.par))) return rc;
+        if (st.atm.sigma_c)
+            return set_error(PZ_E_UNSUPPORTED, "the batched launch has no scattering transfer (use synth_forward)");
         if (!st.F || !st.Fc) return set_error(PZ_E_INVALID_ARG, "every star needs F and Fc");
         if (st.y && !(st.sigma > 0.0f)) return set_error(PZ_E_INVALID_ARG, "sigma must be > 0 with a target y");
         const pz_plan* p = st.plan;

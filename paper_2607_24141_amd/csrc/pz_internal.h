@@ -60,6 +60,13 @@ struct StarDev {
     const double* U;
     const double* mass;
     double kappa0, lam_ref_nm, alpha;
+    const double* sigma_c;       // [D] continuum scattering at lambda_ref, or null (S = B)
+    double sigma_alpha;
+    bool scatter;
+    int sc_max_iter;
+    double sc_tol;
+    double* sc;                  // scattering workspace, [SC_NARR][D][Npad] float64
+    int* sc_iters;               // [3][Npad] iterations used (forward total, continuum, adjoint)
     // corrections (caller device memory; may be null except xi)
     const float* dgf;
     const float* ddamp;
@@ -96,6 +103,7 @@ struct StarDev {
 };
 
 static constexpr int RCHUNK = 2048;      // lines per reduction partial
+static constexpr int SC_WS_ARRAYS = 17;  // [D][Npad] float64 arrays of the scattering workspace
 
 // Kernel launchers (pz_kernels.hip).  Each enqueues on the stream and returns
 // the hipError_t of the launch.
@@ -151,6 +159,13 @@ struct pz_plan {
     bool prof;
     int prof_n[PZ_N_STAGES];
     hipEvent_t* prof_ev;  // [PZ_N_STAGES][PZ_PROFILE_SLOTS][2], created on first enable
+    // transfer with scattering (PZ_FLAG_SCATTERING)
+    bool scatter_ws;
+    double* sc;
+    int* sc_iters;
+    int sc_max_iter;
+    double sc_tol;
+    bool sc_ok;          // the scattering source functions match the recorded workspace
     // who last wrote kappa / lp (see synth_backward)
     bool ws_valid;
     pz_atmos ws_atm;

@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "pz_stages.h"
+#include "pz_scatter.h"
 
 namespace pz {
 
@@ -61,6 +62,14 @@ int opacity_grid(int tile_px) {
 __global__ __launch_bounds__(256) void k_flux(StarDev s) { dev_flux(s, blockIdx.x * blockDim.x + threadIdx.x); }
 
 __global__ __launch_bounds__(64) void k_flux_e2(StarDev s) { dev_flux_e2(s, blockIdx.x * blockDim.x + threadIdx.x); }
+
+__global__ __launch_bounds__(64) void k_flux_scatter(StarDev s) {
+    dev_flux_scatter(s, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_reverse_scatter(StarDev s) {
+    dev_reverse_scatter(s, blockIdx.x * blockDim.x + threadIdx.x);
+}
 
 __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, int quad, float* F) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,7 +184,9 @@ hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
 }
 
 hipError_t launch_flux(const StarDev& s, hipStream_t st) {
-    if (s.quad == PZ_QUAD_E2)
+    if (s.scatter)
+        k_flux_scatter<<<(s.N + 63) / 64, 64, 0, st>>>(s);
+    else if (s.quad == PZ_QUAD_E2)
         k_flux_e2<<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else
         k_flux<<<(s.N + 255) / 256, 256, 0, st>>>(s);
@@ -183,7 +194,9 @@ hipError_t launch_flux(const StarDev& s, hipStream_t st) {
 }
 
 hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st) {
-    if (s.quad == PZ_QUAD_E2)
+    if (s.scatter)
+        k_reverse_scatter<<<(s.N + 63) / 64, 64, 0, st>>>(s);
+    else if (s.quad == PZ_QUAD_E2)
         k_reverse_scan_e2<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else
         k_reverse_scan<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);

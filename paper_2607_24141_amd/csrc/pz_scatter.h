@@ -1,0 +1,531 @@
+// Transfer with continuum scattering (Sec. 2.1, Eqs. 3 and 6-8), per pixel in
+// float64.  With sigma_c the scattering opacity per unit mass,
+//   chi = kappa_abs + sigma_c,  eps = kappa_abs / chi,  S = eps B + (1 - eps) J,
+// kappa_abs = kappa_c + sum kappa_line (total branch) or kappa_c (continuum
+// branch).  J = Lambda S is the mean intensity of the discretised formal
+// solution (piecewise-linear S in tau, linear extrapolation to tau = 0 over the
+// surface segment, diffusion lower boundary I = S + mu dS/dtau; inward I = 0 at
+// tau = 0), J_j = 1/2 sum_k w_k (I+_j(mu_k) + I-_j(mu_k)) on the 3-point
+// Gauss-Legendre nodes of the flux.
+//
+// Forward: the fixed point S* = eps B + (1 - eps) Lambda S* by accelerated
+// Lambda iteration (Jacobi with the diagonal Lambda*_jj of the same operator):
+//   S <- S + (eps B + (1 - eps) Lambda S - S) / (1 - (1 - eps) Lambda*),
+// from S = B until max_j |dS_j / S_j| <= tol (or the iteration cap), then the
+// emergent flux F = 2 pi sum_k w_k mu_k I+(0, mu_k).
+//
+// Backward (total branch): with gS = dF/dS* G and gtau the direct flux terms,
+// the adjoint lambda solves (I - diag(1 - eps) Lambda)^T lambda = gS by the same
+// preconditioned iteration with Lambda^T; then
+//   dL/deps_j = lambda_j (B_j - J*_j),
+//   dL/dtau  += VJP of J(S*, tau) with the cotangent (1 - eps) lambda,
+//   dL/dchi   = trapezoid adjoint of dL/dtau,
+//   dL/dkappa_line_j = dL/dchi_j + dL/deps_j sigma_j / chi_j^2.
+// Workspace columns are [D] with stride Npad (coalesced across pixels).
+#pragma once
+
+namespace pz {
+
+struct Col {
+    double* p;
+    size_t st;
+    __device__ __forceinline__ double& operator[](int j) const { return p[(size_t)j * st]; }
+};
+
+// workspace arrays (each [D][Npad] float64): B, then per branch b (tau, eps, S, J, Ld), then the backward ones
+enum { SC_B = 0, SC_BR = 1, SC_TAU = 0, SC_EPS = 1, SC_S = 2, SC_J = 3, SC_LD = 4, SC_PER_BR = 5,
+       SC_LAM = 11, SC_RHS = 12, SC_GT = 13, SC_IS = 14, SC_NARR = 17 };
+static_assert(SC_NARR == SC_WS_ARRAYS, "scattering workspace size");
+
+__device__ __forceinline__ Col sc_col(const StarDev& s, int id, int i) {
+    return Col{s.sc + (size_t)id * s.D * s.Npad + i, (size_t)s.Npad};
+}
+__device__ __forceinline__ Col sc_bcol(const StarDev& s, int b, int k, int i) {
+    return sc_col(s, SC_BR + SC_PER_BR * b + k, i);
+}
+__device__ __forceinline__ double sc_mu(int k) { return k == 0 ? kMu0 : (k == 1 ? kMu1 : kMu2); }
+__device__ __forceinline__ double sc_hw(int k) { return k == 1 ? 0.5 * 8.0 / 18.0 : 0.5 * 5.0 / 18.0; }   // w_k / 2
+
+// J = Lambda S
+__device__ inline void sc_lambda(int D, const Col& tau, const Col& S, const Col& J) {
+    double I[3];
+    {   // inward, from the surface
+        const double t0 = tau[0], S0 = S[0];
+        const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
+            I[k] = S0 * et.om + (S_top - S0) * et.lw;
+            acc += sc_hw(k) * I[k];
+        }
+        J[0] = acc;
+    }
+    double ta = tau[0], Sa = S[0];
+    for (int j = 1; j < D; ++j) {
+        const double tb = tau[j], Sb = S[j];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64((tb - ta) / sc_mu(k));
+            I[k] = I[k] * et.e + Sb * et.om + (Sa - Sb) * et.lw;
+            acc += sc_hw(k) * I[k];
+        }
+        J[j] = acc;
+        ta = tb;
+        Sa = Sb;
+    }
+    {   // outward, from the diffusion boundary
+        const double SD = S[D - 1];
+        const double grad = (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            I[k] = SD + sc_mu(k) * grad;
+            acc += sc_hw(k) * I[k];
+        }
+        J[D - 1] += acc;
+    }
+    double tb = tau[D - 1], Sb = S[D - 1];
+    for (int j = D - 2; j >= 0; --j) {
+        const double t = tau[j], Sj = S[j];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64((tb - t) / sc_mu(k));
+            I[k] = I[k] * et.e + Sj * et.om + (Sb - Sj) * et.lw;
+            acc += sc_hw(k) * I[k];
+        }
+        J[j] += acc;
+        tb = t;
+        Sb = Sj;
+    }
+}
+
+// out = Lambda^T v
+__device__ inline void sc_lambda_T(int D, const Col& tau, const Col& v, const Col& out) {
+    for (int j = 0; j < D; ++j) out[j] = 0.0;
+    double G[3] = {0.0, 0.0, 0.0};
+    // reverse of the inward sweep (deepest first)
+    for (int j = D - 1; j >= 1; --j) {
+        const double vj = v[j], x0 = tau[j] - tau[j - 1];
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G[k] += sc_hw(k) * vj;
+            const ExpTerms64 et = exp_terms64(x0 / sc_mu(k));
+            a += G[k] * (et.om - et.lw);
+            b += G[k] * et.lw;
+            G[k] *= et.e;
+        }
+        out[j] += a;
+        out[j - 1] += b;
+    }
+    {
+        const double t0 = tau[0], c = t0 / (tau[1] - t0), v0 = v[0];
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G[k] += sc_hw(k) * v0;
+            const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
+            a += G[k] * (et.om + c * et.lw);
+            b -= G[k] * c * et.lw;
+        }
+        out[0] += a;
+        out[1] += b;
+    }
+    // reverse of the outward sweep (surface first)
+    G[0] = G[1] = G[2] = 0.0;
+    for (int j = 0; j < D - 1; ++j) {
+        const double vj = v[j], x0 = tau[j + 1] - tau[j];
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G[k] += sc_hw(k) * vj;
+            const ExpTerms64 et = exp_terms64(x0 / sc_mu(k));
+            a += G[k] * (et.om - et.lw);
+            b += G[k] * et.lw;
+            G[k] *= et.e;
+        }
+        out[j] += a;
+        out[j + 1] += b;
+    }
+    {
+        const double g = 1.0 / (tau[D - 1] - tau[D - 2]), vD = v[D - 1];
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G[k] += sc_hw(k) * vD;
+            a += G[k] * (1.0 + sc_mu(k) * g);
+            b -= G[k] * sc_mu(k) * g;
+        }
+        out[D - 1] += a;
+        out[D - 2] += b;
+    }
+}
+
+// Lambda*_jj: the coefficient of S_j in J_j
+__device__ inline void sc_lambda_diag(int D, const Col& tau, const Col& Ld) {
+    const double t0 = tau[0], c = t0 / (tau[1] - t0), gD = 1.0 / (tau[D - 1] - tau[D - 2]);
+    for (int j = 0; j < D; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            double out, in;
+            if (j == D - 1) {
+                out = 1.0 + mu * gD;
+            } else {
+                const ExpTerms64 et = exp_terms64((tau[j + 1] - tau[j]) / mu);
+                out = et.om - et.lw;
+                if (j == D - 2) out -= et.e * mu * gD;
+            }
+            if (j == 0) {
+                const ExpTerms64 et = exp_terms64(t0 / mu);
+                in = et.om + c * et.lw;
+            } else {
+                const ExpTerms64 et = exp_terms64((tau[j] - tau[j - 1]) / mu);
+                in = et.om - et.lw;
+                if (j == 1) in -= et.e * c * exp_terms64(t0 / mu).lw;
+            }
+            acc += sc_hw(k) * (out + in);
+        }
+        Ld[j] = acc;
+    }
+}
+
+// Emergent flux of S (Eq. 8)
+__device__ inline double sc_flux(int D, const Col& tau, const Col& S) {
+    double I[3];
+    const double SD = S[D - 1];
+    const double grad = (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) I[k] = SD + sc_mu(k) * grad;
+    double tb = tau[D - 1], Sb = SD;
+    for (int j = D - 2; j >= 0; --j) {
+        const double t = tau[j], Sj = S[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64((tb - t) / sc_mu(k));
+            I[k] = I[k] * et.e + Sj * et.om + (Sb - Sj) * et.lw;
+        }
+        tb = t;
+        Sb = Sj;
+    }
+    const double t0 = tau[0], S0 = S[0];
+    const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+    double F = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
+        const double I0 = I[k] * et.e + S_top * et.om + (S0 - S_top) * et.lw;
+        F += 2.0 * PI * 2.0 * sc_hw(k) * sc_mu(k) * I0;
+    }
+    return F;
+}
+
+// Outward intensities I+_j(mu_k) into IS[k] (bottom-up)
+__device__ inline void sc_store_out(int D, const Col& tau, const Col& S, const Col* IS) {
+    const double SD = S[D - 1];
+    const double grad = (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
+    double I[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        I[k] = SD + sc_mu(k) * grad;
+        IS[k][D - 1] = I[k];
+    }
+    double tb = tau[D - 1], Sb = SD;
+    for (int j = D - 2; j >= 0; --j) {
+        const double t = tau[j], Sj = S[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64((tb - t) / sc_mu(k));
+            I[k] = I[k] * et.e + Sj * et.om + (Sb - Sj) * et.lw;
+            IS[k][j] = I[k];
+        }
+        tb = t;
+        Sb = Sj;
+    }
+}
+
+// Inward intensities I-_j(mu_k) into IS[k] (top-down)
+__device__ inline void sc_store_in(int D, const Col& tau, const Col& S, const Col* IS) {
+    const double t0 = tau[0], S0 = S[0];
+    const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+    double I[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
+        I[k] = S0 * et.om + (S_top - S0) * et.lw;
+        IS[k][0] = I[k];
+    }
+    double ta = t0, Sa = S0;
+    for (int j = 1; j < D; ++j) {
+        const double tb = tau[j], Sb = S[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64((tb - ta) / sc_mu(k));
+            I[k] = I[k] * et.e + Sb * et.om + (Sa - Sb) * et.lw;
+            IS[k][j] = I[k];
+        }
+        ta = tb;
+        Sa = Sb;
+    }
+}
+
+// d(S_top)/d(tau_0), d(S_top)/d(tau_1) with S_top = S_0 - tau_0 (S_1 - S_0) / (tau_1 - tau_0)
+__device__ __forceinline__ void sc_top_dtau(const Col& tau, const Col& S, double& d0, double& d1) {
+    const double t0 = tau[0], dt = tau[1] - t0, sig = (S[1] - S[0]) / dt;
+    d0 = -sig - t0 * sig / dt;
+    d1 = t0 * sig / dt;
+}
+
+// Flux VJP for the seed G: writes dF/dS G into gS and adds the tau terms to gt.
+__device__ inline void sc_flux_vjp(int D, const Col& tau, const Col& S, double G, const Col& gS, const Col& gt,
+                                   const Col* IS) {
+    sc_store_out(D, tau, S, IS);
+    for (int j = 0; j < D; ++j) gS[j] = 0.0;
+    const double t0 = tau[0], S0 = S[0], dt01 = tau[1] - t0;
+    const double S_top = S0 - t0 * (S[1] - S0) / dt01;
+    double d0, d1;
+    sc_top_dtau(tau, S, d0, d1);
+    double Gk[3];
+    double gStop = 0.0, gS0 = 0.0, gt0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double mu = sc_mu(k);
+        const double g0 = G * 2.0 * PI * 2.0 * sc_hw(k) * mu;      // dL/dI(0, mu_k)
+        const ExpTerms64 et = exp_terms64(t0 / mu);
+        const double Iin = IS[k][0];                                  // I+ at tau_0
+        gt0 += g0 * (-Iin * et.e + S_top * et.e + (S0 - S_top) * et.dlw) / mu;
+        gStop += g0 * (et.om - et.lw);
+        gS0 += g0 * et.lw;
+        Gk[k] = g0 * et.e;                                            // dL/dI+(tau_0)
+    }
+    gS[0] += gS0 + gStop * (1.0 + t0 / dt01);
+    gS[1] += gStop * (-t0 / dt01);
+    gt[0] += gt0 + gStop * d0;
+    gt[1] += gStop * d1;
+    for (int j = 0; j < D - 1; ++j) {
+        const double t = tau[j], tn = tau[j + 1], Sj = S[j], Sn = S[j + 1];
+        double a = 0.0, b = 0.0, gx = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            const ExpTerms64 et = exp_terms64((tn - t) / mu);
+            gx += Gk[k] * (-IS[k][j + 1] * et.e + Sj * et.e + (Sn - Sj) * et.dlw) / mu;
+            a += Gk[k] * (et.om - et.lw);
+            b += Gk[k] * et.lw;
+            Gk[k] *= et.e;
+        }
+        gS[j] += a;
+        gS[j + 1] += b;
+        gt[j + 1] += gx;
+        gt[j] -= gx;
+    }
+    {
+        const double dS = S[D - 1] - S[D - 2], dt = tau[D - 1] - tau[D - 2];
+        double a = 0.0, b = 0.0, gd = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            a += Gk[k] * (1.0 + mu / dt);
+            b -= Gk[k] * mu / dt;
+            gd += Gk[k] * (-mu * dS / (dt * dt));
+        }
+        gS[D - 1] += a;
+        gS[D - 2] += b;
+        gt[D - 1] += gd;
+        gt[D - 2] -= gd;
+    }
+}
+
+// Adds to gt the tau part of the VJP of J(S, tau) for the cotangent u.
+__device__ inline void sc_lambda_tau_vjp(int D, const Col& tau, const Col& S, const Col& u, const Col& gt,
+                                         const Col* IS) {
+    double G[3];
+    // inward: forward profiles, then the reverse sweep from the deepest layer
+    sc_store_in(D, tau, S, IS);
+    G[0] = G[1] = G[2] = 0.0;
+    for (int j = D - 1; j >= 1; --j) {
+        const double uj = u[j], t = tau[j], tp = tau[j - 1], Sj = S[j], Sp = S[j - 1];
+        double gx = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            G[k] += sc_hw(k) * uj;
+            const ExpTerms64 et = exp_terms64((t - tp) / mu);
+            gx += G[k] * (-IS[k][j - 1] * et.e + Sj * et.e + (Sp - Sj) * et.dlw) / mu;
+            G[k] *= et.e;
+        }
+        gt[j] += gx;
+        gt[j - 1] -= gx;
+    }
+    {
+        const double t0 = tau[0], S0 = S[0];
+        const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+        double d0, d1;
+        sc_top_dtau(tau, S, d0, d1);
+        double gx = 0.0, gStop = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            G[k] += sc_hw(k) * u[0];
+            const ExpTerms64 et = exp_terms64(t0 / mu);
+            gx += G[k] * (S0 * et.e + (S_top - S0) * et.dlw) / mu;
+            gStop += G[k] * et.lw;
+        }
+        gt[0] += gx + gStop * d0;
+        gt[1] += gStop * d1;
+    }
+    // outward: forward profiles, then the reverse sweep from the surface
+    sc_store_out(D, tau, S, IS);
+    G[0] = G[1] = G[2] = 0.0;
+    for (int j = 0; j < D - 1; ++j) {
+        const double uj = u[j], t = tau[j], tn = tau[j + 1], Sj = S[j], Sn = S[j + 1];
+        double gx = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            G[k] += sc_hw(k) * uj;
+            const ExpTerms64 et = exp_terms64((tn - t) / mu);
+            gx += G[k] * (-IS[k][j + 1] * et.e + Sj * et.e + (Sn - Sj) * et.dlw) / mu;
+            G[k] *= et.e;
+        }
+        gt[j + 1] += gx;
+        gt[j] -= gx;
+    }
+    {
+        const double dS = S[D - 1] - S[D - 2], dt = tau[D - 1] - tau[D - 2];
+        double gd = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G[k] += sc_hw(k) * u[D - 1];
+            gd += G[k] * (-sc_mu(k) * dS / (dt * dt));
+        }
+        gt[D - 1] += gd;
+        gt[D - 2] -= gd;
+    }
+}
+
+struct ScPixel {
+    double kc, c1, c2, fs;   // continuum, Planck constants, sigma scale (lambda/lambda_ref)^sigma_alpha
+};
+
+__device__ __forceinline__ ScPixel sc_pixel(const StarDev& s, int i) {
+    const double lnl = log(s.lam_first_nm) + (double)i * s.h;
+    const double lam_cm = exp(lnl) * 1.0e-7;
+    ScPixel p;
+    p.kc = s.kappa0 * exp(s.alpha * (lnl - log(s.lam_ref_nm)));
+    const double l2 = lam_cm * lam_cm;
+    p.c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
+    p.c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
+    p.fs = exp(s.sigma_alpha * (lnl - log(s.lam_ref_nm)));
+    return p;
+}
+
+// tau, eps (and B for b = 0) of branch b; S starts at B
+__device__ inline void sc_setup(const StarDev& s, int i, int b, const ScPixel& p) {
+    const int D = s.D;
+    const Col B = sc_col(s, SC_B, i), tau = sc_bcol(s, b, SC_TAU, i), eps = sc_bcol(s, b, SC_EPS, i),
+              S = sc_bcol(s, b, SC_S, i);
+    const float* kl = s.kappa + i;
+    double chi_prev = 0.0, t = 0.0;
+    for (int j = 0; j < D; ++j) {
+        const double ka = p.kc + (b == 0 ? (double)kl[(size_t)j * s.Npad] : 0.0);
+        const double chi = ka + s.sigma_c[j] * p.fs;
+        t = (j == 0) ? chi * s.m[0] : t + 0.5 * (chi_prev + chi) * (s.m[j] - s.m[j - 1]);
+        chi_prev = chi;
+        tau[j] = t;
+        eps[j] = ka / chi;
+        if (b == 0) B[j] = p.c1 / expm1(p.c2 / s.T[j]);
+        S[j] = B[j];
+    }
+    sc_lambda_diag(D, tau, sc_bcol(s, b, SC_LD, i));
+}
+
+// Accelerated Lambda iteration of branch b; returns the iterations used.
+__device__ inline int sc_iterate(const StarDev& s, int i, int b) {
+    const int D = s.D;
+    const Col B = sc_col(s, SC_B, i), tau = sc_bcol(s, b, SC_TAU, i), eps = sc_bcol(s, b, SC_EPS, i),
+              S = sc_bcol(s, b, SC_S, i), J = sc_bcol(s, b, SC_J, i), Ld = sc_bcol(s, b, SC_LD, i);
+    int it = 0;
+    while (it < s.sc_max_iter) {
+        ++it;
+        sc_lambda(D, tau, S, J);
+        double dmax = 0.0;
+        for (int j = 0; j < D; ++j) {
+            const double e = eps[j], Sj = S[j];
+            const double Sn = Sj + (e * B[j] + (1.0 - e) * J[j] - Sj) / (1.0 - (1.0 - e) * Ld[j]);
+            dmax = fmax(dmax, fabs(Sn - Sj) / fabs(Sn));
+            S[j] = Sn;
+        }
+        if (dmax <= s.sc_tol) break;
+    }
+    return it;
+}
+
+__device__ inline void dev_flux_scatter(const StarDev& s, int i) {
+    if (i >= s.N) return;
+    const ScPixel p = sc_pixel(s, i);
+    for (int b = 0; b < 2; ++b) {
+        sc_setup(s, i, b, p);
+        const int it = sc_iterate(s, i, b);
+        if (s.sc_iters) s.sc_iters[b * s.Npad + i] = it;
+        const double F = sc_flux(s.D, sc_bcol(s, b, SC_TAU, i), sc_bcol(s, b, SC_S, i));
+        float* out = b == 0 ? s.F : s.Fc;
+        if (out) out[i] = (float)F;
+    }
+}
+
+// Backward of the total branch: writes dL/dkappa_line into gk.
+__device__ inline void dev_reverse_scatter(const StarDev& s, int i) {
+    if (i >= s.N) return;
+    const int D = s.D;
+    const ScPixel p = sc_pixel(s, i);
+    const Col B = sc_col(s, SC_B, i), tau = sc_bcol(s, 0, SC_TAU, i), eps = sc_bcol(s, 0, SC_EPS, i),
+              S = sc_bcol(s, 0, SC_S, i), J = sc_bcol(s, 0, SC_J, i), Ld = sc_bcol(s, 0, SC_LD, i);
+    const Col lam = sc_col(s, SC_LAM, i), rhs = sc_col(s, SC_RHS, i), gt = sc_col(s, SC_GT, i);
+    const Col U = sc_bcol(s, 1, SC_S, i), T = sc_bcol(s, 1, SC_J, i);   // continuum-branch columns as scratch
+    const Col IS[3] = {sc_col(s, SC_IS, i), sc_col(s, SC_IS + 1, i), sc_col(s, SC_IS + 2, i)};
+    for (int j = 0; j < D; ++j) gt[j] = 0.0;
+    sc_flux_vjp(D, tau, S, (double)s.dLdF[i], rhs, gt, IS);
+    // adjoint fixed point: lambda = rhs + Lambda^T ((1 - eps) lambda)
+    for (int j = 0; j < D; ++j) lam[j] = rhs[j];
+    int it = 0;
+    while (it < s.sc_max_iter) {
+        ++it;
+        for (int j = 0; j < D; ++j) U[j] = (1.0 - eps[j]) * lam[j];
+        sc_lambda_T(D, tau, U, T);
+        double dmax = 0.0, lmax = 0.0;
+        for (int j = 0; j < D; ++j) {
+            const double e = eps[j], lj = lam[j];
+            const double ln = lj + (rhs[j] + T[j] - lj) / (1.0 - (1.0 - e) * Ld[j]);
+            dmax = fmax(dmax, fabs(ln - lj));
+            lmax = fmax(lmax, fabs(ln));
+            lam[j] = ln;
+        }
+        if (dmax <= s.sc_tol * lmax) break;
+    }
+    if (s.sc_iters) s.sc_iters[2 * s.Npad + i] = it;
+    // J* and the eps and tau terms of the fixed point
+    sc_lambda(D, tau, S, J);
+    for (int j = 0; j < D; ++j) U[j] = (1.0 - eps[j]) * lam[j];
+    sc_lambda_tau_vjp(D, tau, S, U, gt, IS);
+    // dL/dchi by the trapezoid adjoint, then dL/dkappa_line
+    const float* kl = s.kappa + i;
+    float* out = s.gk + i;
+    double suffix = 0.0, gnext = 0.0;
+    for (int j = D - 1; j >= 0; --j) {
+        suffix += gt[j];
+        double gchi = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
+        gchi += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
+        gnext = suffix;
+        const double sig = s.sigma_c[j] * p.fs;
+        const double chi = p.kc + (double)kl[(size_t)j * s.Npad] + sig;
+        const double geps = lam[j] * (B[j] - J[j]);
+        out[(size_t)j * s.Npad] = (float)(gchi + geps * sig / (chi * chi));
+    }
+}
+
+}  // namespace pz

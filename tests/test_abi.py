@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(pz):
 
 
 def test_version(pz):
-    assert pz.pz_version() == pz.ABI_VERSION == 3
+    assert pz.pz_version() == pz.ABI_VERSION == 4
 
 
 def _lines(pz, L=3, **over):
@@ -61,7 +61,8 @@ def _create(pz, grid=None, lines=None, S=2, D=8, opts=None):
 
 @pytest.mark.parametrize("case,code", [
     ("N", -2), ("R", -1), ("lam", -1), ("D", -2), ("Dbig", -2), ("S", -2), ("W", -1), ("quad", -1),
-    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5), ("eta", -1), ("eta_nan", -1)])
+    ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5), ("eta", -1), ("eta_nan", -1),
+    ("scat_iter", -1), ("scat_tol", -1), ("scat_e2", -6)])
 def test_plan_validation(pz, case, code):
     import numpy as np
     kw = {}
@@ -84,11 +85,17 @@ def test_plan_validation(pz, case, code):
     elif case == "tile":
         kw["opts"] = pz.pz_options(0.3, 0, 48, 0, 0)
     elif case == "flags":
-        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 2)
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 4)
     elif case == "eta":
         kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 0, -1e-3)
     elif case == "eta_nan":
         kw["opts"] = pz.pz_options(0.3, 0, 0, 0, 0, float("nan"))
+    elif case == "scat_iter":
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, pz.PZ_FLAG_SCATTERING, 0.0, -3)
+    elif case == "scat_tol":
+        kw["opts"] = pz.pz_options(0.3, 0, 0, 0, pz.PZ_FLAG_SCATTERING, 0.0, 0, float("inf"))
+    elif case == "scat_e2":
+        kw["opts"] = pz.pz_options(0.3, pz.PZ_QUAD_E2, 0, 0, pz.PZ_FLAG_SCATTERING)
     elif case == "species":
         kw["lines"] = _lines(pz, sp=np.array([0, 5, 0], np.int32))
     elif case == "ion":
@@ -108,6 +115,7 @@ def test_entry_points_reject_null_before_device_work(pz):
     assert pz.lib.pz_debug_formal_solve(8, 4, None, None, 0, None, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.synth_batch(None, 1, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.pz_select_lines(None, None, None, 1e-3, 1e-3, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
+    assert pz.lib.pz_scatter_iterations(None, None) == pz.PZ_E_INVALID_ARG
     assert pz.lib.pz_plan_info(None, None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
 
 
