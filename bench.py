@@ -6,14 +6,15 @@ resident in HBM, K timed steps between device synchronisations.  A step is
 one whole forward synthesis (populations, line parameters, windowed Voigt
 opacity, depth scan and Gauss-3 flux for both branches).  Extra fields: the
 forward+backward step (chi^2 loss seed and the adjoint for all 4e5 + 20 + 1
-corrections), the centre test, the line-selection keep test (and the forward
+corrections), the centre test, continuum scattering (the source function
+iterated to its fixed point, forward and forward+backward), the line-selection keep test (and the forward
 of its kept subset), the instrument operator, the line calibration
 (objective evaluation and L-BFGS updates over 25,147 correction groups of a
 two-star, three-spectrum fit) and the batched launch over 256 stars, the roofline of the
 dominant kernel (opacity) and the FP64 CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                      [--modes fwd,fwdbwd,center,select,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
+                      [--modes fwd,fwdbwd,center,select,scatter,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -105,7 +106,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fwd,fwdbwd,center,select,instrument,calibration,batch")
+    ap.add_argument("--modes", default="fwd,fwdbwd,center,select,scatter,instrument,calibration,batch")
     ap.add_argument("--cal-updates", type=int, default=40, help="L-BFGS updates of the calibration block")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
@@ -254,6 +255,39 @@ def main():
                             "kept_fraction": idx.size / L, "fwd_ms_selected": ms_sf,
                             "speedup_vs_full_fwd": ms_fwd / ms_sf, "max_abs_dflux_vs_full": dmax,
                             "max_rel_dF_vs_full": dF_rel, "pixels_changed": n_diff}
+        splan.destroy()
+
+    # ---- transfer with continuum scattering (Eq. 6 iterated to its fixed point), same lines
+    if "scatter" in modes:
+        import copy
+        swl = copy.deepcopy(wl)
+        swl.atm.sigma_c = np.full(wl.atm.D, 0.5 * wl.atm.kappa0)     # grey scattering, half the continuum
+        swl.atm.sigma_alpha = 0.0
+        splan = pz.plan_for(swl, tile_px=plan.tile_px)
+        satm = pz.Atmos(swl.atm)
+        sfwd = lambda: pz.synth_forward(splan, satm, par, F, Fc)
+        splan.profile(True)
+        ms_sf, _ = timed(sfwd, args.steps, args.warmup, torch)
+        sprof = splan.profile_read()
+        splan.profile(False)
+        it_f = splan.scatter_iterations()
+        gS = torch.empty_like(F)
+        gl = [torch.empty(L, device=dev), torch.empty(L, device=dev), torch.empty(S, device=dev),
+              torch.empty(1, device=dev)]
+        ys = torch.ones_like(F)
+
+        def sfb():
+            pz.synth_forward(splan, satm, par, F, Fc)
+            pz.pz_chi2_seed(F, Fc, ys, 0.01, gS, None, None)
+            pz.synth_backward(splan, satm, par, gS, *gl)
+
+        ms_sfb, _ = timed(sfb, args.steps, args.warmup, torch)
+        it_b = splan.scatter_iterations()
+        out["scattering"] = {"sigma_c_over_kappa_c": 0.5, "fwd_spectra_per_s": 1000.0 / ms_sf, "fwd_ms": ms_sf,
+                             "fwd_bwd_spectra_per_s": 1000.0 / ms_sfb, "fwd_bwd_ms": ms_sfb,
+                             "flux_stage_ms": sprof["flux"][0] / max(sprof["flux"][1], 1),
+                             "max_iterations_fwd": [int(it_f[0]), int(it_f[1])],
+                             "max_iterations_adjoint": int(it_b[2])}
         splan.destroy()
 
     # ---- the instrument operator of Eq. 31 on APOGEE-like pixels (one flux pair)
