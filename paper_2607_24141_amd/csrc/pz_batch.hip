@@ -150,6 +150,7 @@ __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ sta
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void kb_gather(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     __shared__ int s_it;
     __shared__ float4 pw[PZ_PW_N * 8];
+    __shared__ float4 lq[512 / WAVE][MAXD];
     load_pw_table(pw, true);                           // visible after the first item fetch's barrier
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     for (;;) {
@@ -159,7 +160,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
         const StarDev& s = stars[w.x];
         for (int q = wave; q < GATHER_ITEM; q += 512 / WAVE) {
             const int l = __builtin_amdgcn_readfirstlane(w.y * GATHER_ITEM + q);
-            dev_gather(s, l, lane, pw);
+            // the row is private to this wavefront: order its writes before the
+            // reads and the previous line's reads before the writes
+            __builtin_amdgcn_wave_barrier();
+            stage_line_params(s, l, lane, lq[wave]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            dev_gather(s, l, lane, pw, lq[wave]);
         }
     }
 }

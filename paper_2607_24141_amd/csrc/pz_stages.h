@@ -767,18 +767,18 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 
 // One call per wavefront; l must be wavefront-uniform; pw holds the H and L
-// core tables (LDS).
+// core tables and lq the line's per-depth parameters lp[l][0..D) (both LDS).
 // FAM: the damping term is split over the three families by their share of
 // the width at each depth, w_beta = Gamma_beta / Gamma.
 template <bool CT, bool FAM>
-__device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, const float4* pw) {
+__device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, const float4* pw, const float4* lq) {
     constexpr int WPX = 8, NDG = 8, DPT = (MAXD + NDG - 1) / NDG;
     const int px = lane % WPX, dg = lane / WPX;
     int ilo = s.ln.ilo[l], ihi = s.ln.ihi[l];
     const int ic = s.ln.ic[l];
     const float delta = s.ln.delta[l];
     const int D = s.D;
-    const float4* lp = s.lp + (size_t)l * D;
+    const float4* lp = lq;
     const float* zm = CT ? s.zmax + (size_t)l * D : nullptr;
     if (CT) {
         // pixels whose detuning x = expm1(delta - k h) can reach the line's
@@ -849,19 +849,26 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
     }
 }
 
-__device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, const float4* pw) {
+__device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, const float4* pw, const float4* lq) {
     if (l >= s.L) return;
     if (s.fam) {
         if (s.center)
-            gather_body<true, true>(s, l, lane, pw);
+            gather_body<true, true>(s, l, lane, pw, lq);
         else
-            gather_body<false, true>(s, l, lane, pw);
+            gather_body<false, true>(s, l, lane, pw, lq);
     } else {
         if (s.center)
-            gather_body<true, false>(s, l, lane, pw);
+            gather_body<true, false>(s, l, lane, pw, lq);
         else
-            gather_body<false, false>(s, l, lane, pw);
+            gather_body<false, false>(s, l, lane, pw, lq);
     }
+}
+
+// A wavefront copies line l's per-depth parameters to its LDS row (l must be
+// wavefront-uniform; nothing for l >= L).
+__device__ __forceinline__ void stage_line_params(const StarDev& s, int l, int lane, float4* lq) {
+    if (l >= s.L) return;
+    for (int k = lane; k < s.D; k += WAVE) lq[k] = s.lp[(size_t)l * s.D + k];
 }
 
 // ----------------------------------------------------------- reductions
