@@ -35,9 +35,12 @@ METRIC = "spectra/s, Voigt evals/s: fwd, fwd+bwd, batched vs plain fwd at 1e-4 r
 FLOPS_PER_EVAL = 34
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 # sources of the opacity kernel: a committed HBM-traffic measurement is used only if they are unchanged
-KERNEL_SOURCES = ("paper_2607_24141_amd/csrc/pz_kernels.hip", "paper_2607_24141_amd/csrc/pz_stages.h",
-                  "paper_2607_24141_amd/csrc/pz_voigt.h", "paper_2607_24141_amd/csrc/voigt_consts.h",
-                  "paper_2607_24141_amd/csrc/pz_internal.h")
+# The opacity kernel's code: its tile body and the Voigt evaluator, plus the
+# kernel's own definition in pz_kernels.hip (other code in that file is not
+# part of it).
+KERNEL_SOURCES = ("paper_2607_24141_amd/csrc/pz_opacity.h", "paper_2607_24141_amd/csrc/pz_voigt.h",
+                  "paper_2607_24141_amd/csrc/voigt_consts.h")
+KERNEL_DEF = ("paper_2607_24141_amd/csrc/pz_kernels.hip", "void k_opacity(")
 
 
 def log(*a):
@@ -49,6 +52,11 @@ def kernel_hash():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, KERNEL_DEF[0])) as fh:
+        txt = fh.read()
+    i = txt.index(KERNEL_DEF[1])
+    i = txt.rindex("\n", 0, txt.rindex("\n", 0, i)) + 1      # from the template line above
+    h.update(txt[i:txt.index("\n}\n", i) + 3].encode())
     return h.hexdigest()[:16]
 
 
