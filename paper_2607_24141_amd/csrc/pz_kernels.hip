@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_flux(StarDev s) { dev_flux(s, blockIdx.
 
 __global__ __launch_bounds__(64) void k_flux_e2(StarDev s) { dev_flux_e2(s, blockIdx.x * blockDim.x + threadIdx.x); }
 
-__global__ __launch_bounds__(64) void k_flux_scatter(StarDev s) {
-    dev_flux_scatter(s, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(192) void k_flux_scatter(StarDev s) {
+    dev_flux_scatter(s, blockIdx.x * 64 + threadIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(64) void k_reverse_scatter(StarDev s) {
@@ -188,7 +188,7 @@ hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
 
 hipError_t launch_flux(const StarDev& s, hipStream_t st) {
     if (s.scatter)
-        k_flux_scatter<<<(s.N + 63) / 64, 64, 0, st>>>(s);
+        k_flux_scatter<<<dim3((s.N + 63) / 64, 2), dim3(64, 3), 0, st>>>(s);
     else if (s.quad == PZ_QUAD_E2)
         k_flux_e2<<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else

@@ -12,7 +12,9 @@
 // Lambda iteration (Jacobi with the diagonal Lambda*_jj of the same operator):
 //   S <- S + (eps B + (1 - eps) Lambda S - S) / (1 - (1 - eps) Lambda*),
 // from S = B until max_j |dS_j / S_j| <= tol (or the iteration cap), then the
-// emergent flux F = 2 pi sum_k w_k mu_k I+(0, mu_k).
+// emergent flux F = 2 pi sum_k w_k mu_k I+(0, mu_k).  Six threads per pixel:
+// the two branches, and in each the three ray directions, which sweep their
+// share of J in parallel and then update a third of the depths each.
 //
 // Backward (total branch): with gS = dF/dS* G and gtau the direct flux terms,
 // the adjoint lambda solves (I - diag(1 - eps) Lambda)^T lambda = gS by the same
@@ -32,9 +34,12 @@ struct Col {
     __device__ __forceinline__ double& operator[](int j) const { return p[(size_t)j * st]; }
 };
 
-// workspace arrays (each [D][Npad] float64): B, then per branch b (tau, eps, S, J, Ld), then the backward ones
-enum { SC_B = 0, SC_BR = 1, SC_TAU = 0, SC_EPS = 1, SC_S = 2, SC_J = 3, SC_LD = 4, SC_PER_BR = 5,
-       SC_LAM = 11, SC_RHS = 12, SC_GT = 13, SC_IS = 14, SC_NARR = 17 };
+// workspace arrays (each [D][Npad] float64): per branch b (tau, eps, S, J, Ld, B and the three
+// per-direction parts of J), then the backward ones
+// and the segment coefficients of each direction m (e^-x, 1 - e^-x, lw(x) of the segment ending at
+// depth j, j >= 1, and of the surface segment [0, tau_0] at j = 0)
+enum { SC_BR = 0, SC_TAU = 0, SC_EPS = 1, SC_S = 2, SC_J = 3, SC_LD = 4, SC_B = 5, SC_JM = 6, SC_CE = 9,
+       SC_CO = 12, SC_CL = 15, SC_PER_BR = 18, SC_LAM = 36, SC_RHS = 37, SC_GT = 38, SC_IS = 39, SC_NARR = 42 };
 static_assert(SC_NARR == SC_WS_ARRAYS, "scattering workspace size");
 
 __device__ __forceinline__ Col sc_col(const StarDev& s, int id, int i) {
@@ -162,66 +167,6 @@ __device__ inline void sc_lambda_T(int D, const Col& tau, const Col& v, const Co
         out[D - 1] += a;
         out[D - 2] += b;
     }
-}
-
-// Lambda*_jj: the coefficient of S_j in J_j
-__device__ inline void sc_lambda_diag(int D, const Col& tau, const Col& Ld) {
-    const double t0 = tau[0], c = t0 / (tau[1] - t0), gD = 1.0 / (tau[D - 1] - tau[D - 2]);
-    for (int j = 0; j < D; ++j) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double mu = sc_mu(k);
-            double out, in;
-            if (j == D - 1) {
-                out = 1.0 + mu * gD;
-            } else {
-                const ExpTerms64 et = exp_terms64((tau[j + 1] - tau[j]) / mu);
-                out = et.om - et.lw;
-                if (j == D - 2) out -= et.e * mu * gD;
-            }
-            if (j == 0) {
-                const ExpTerms64 et = exp_terms64(t0 / mu);
-                in = et.om + c * et.lw;
-            } else {
-                const ExpTerms64 et = exp_terms64((tau[j] - tau[j - 1]) / mu);
-                in = et.om - et.lw;
-                if (j == 1) in -= et.e * c * exp_terms64(t0 / mu).lw;
-            }
-            acc += sc_hw(k) * (out + in);
-        }
-        Ld[j] = acc;
-    }
-}
-
-// Emergent flux of S (Eq. 8)
-__device__ inline double sc_flux(int D, const Col& tau, const Col& S) {
-    double I[3];
-    const double SD = S[D - 1];
-    const double grad = (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) I[k] = SD + sc_mu(k) * grad;
-    double tb = tau[D - 1], Sb = SD;
-    for (int j = D - 2; j >= 0; --j) {
-        const double t = tau[j], Sj = S[j];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms64 et = exp_terms64((tb - t) / sc_mu(k));
-            I[k] = I[k] * et.e + Sj * et.om + (Sb - Sj) * et.lw;
-        }
-        tb = t;
-        Sb = Sj;
-    }
-    const double t0 = tau[0], S0 = S[0];
-    const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
-    double F = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
-        const double I0 = I[k] * et.e + S_top * et.om + (S0 - S_top) * et.lw;
-        F += 2.0 * PI * 2.0 * sc_hw(k) * sc_mu(k) * I0;
-    }
-    return F;
 }
 
 // Outward intensities I+_j(mu_k) into IS[k] (bottom-up)
@@ -424,10 +369,10 @@ __device__ __forceinline__ ScPixel sc_pixel(const StarDev& s, int i) {
     return p;
 }
 
-// tau, eps (and B for b = 0) of branch b; S starts at B
+// tau, eps and B of branch b; S starts at B
 __device__ inline void sc_setup(const StarDev& s, int i, int b, const ScPixel& p) {
     const int D = s.D;
-    const Col B = sc_col(s, SC_B, i), tau = sc_bcol(s, b, SC_TAU, i), eps = sc_bcol(s, b, SC_EPS, i),
+    const Col B = sc_bcol(s, b, SC_B, i), tau = sc_bcol(s, b, SC_TAU, i), eps = sc_bcol(s, b, SC_EPS, i),
               S = sc_bcol(s, b, SC_S, i);
     const float* kl = s.kappa + i;
     double chi_prev = 0.0, t = 0.0;
@@ -438,43 +383,159 @@ __device__ inline void sc_setup(const StarDev& s, int i, int b, const ScPixel& p
         chi_prev = chi;
         tau[j] = t;
         eps[j] = ka / chi;
-        if (b == 0) B[j] = p.c1 / expm1(p.c2 / s.T[j]);
-        S[j] = B[j];
+        const double Bj = p.c1 / expm1(p.c2 / s.T[j]);
+        B[j] = Bj;
+        S[j] = Bj;
     }
-    sc_lambda_diag(D, tau, sc_bcol(s, b, SC_LD, i));
 }
 
-// Accelerated Lambda iteration of branch b; returns the iterations used.
-__device__ inline int sc_iterate(const StarDev& s, int i, int b) {
-    const int D = s.D;
-    const Col B = sc_col(s, SC_B, i), tau = sc_bcol(s, b, SC_TAU, i), eps = sc_bcol(s, b, SC_EPS, i),
-              S = sc_bcol(s, b, SC_S, i), J = sc_bcol(s, b, SC_J, i), Ld = sc_bcol(s, b, SC_LD, i);
-    int it = 0;
-    while (it < s.sc_max_iter) {
-        ++it;
-        sc_lambda(D, tau, S, J);
-        double dmax = 0.0;
-        for (int j = 0; j < D; ++j) {
-            const double e = eps[j], Sj = S[j];
-            const double Sn = Sj + (e * B[j] + (1.0 - e) * J[j] - Sj) / (1.0 - (1.0 - e) * Ld[j]);
-            dmax = fmax(dmax, fabs(Sn - Sj) / fabs(Sn));
-            S[j] = Sn;
+// Segment coefficients of direction m (see the workspace layout)
+__device__ inline void sc_coeffs(int D, const Col& tau, int m, const Col& CE, const Col& CO, const Col& CL) {
+    const double mu = sc_mu(m);
+    double ta = 0.0;
+    for (int j = 0; j < D; ++j) {
+        const double tb = tau[j];
+        const ExpTerms64 et = exp_terms64((tb - ta) / mu);
+        CE[j] = et.e;
+        CO[j] = et.om;
+        CL[j] = et.lw;
+        ta = tb;
+    }
+}
+
+// Lambda*_jj for the depths j = m, m + 3, ... (the coefficient of S_j in J_j),
+// from the coefficients of all three directions
+__device__ inline void sc_lambda_diag_part(int D, const Col& tau, const Col& Ld, int m, const Col* CE, const Col* CO,
+                                           const Col* CL) {
+    const double t0 = tau[0], c = t0 / (tau[1] - t0), gD = 1.0 / (tau[D - 1] - tau[D - 2]);
+    for (int j = m; j < D; j += 3) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double mu = sc_mu(k);
+            double out, in;
+            if (j == D - 1) {
+                out = 1.0 + mu * gD;
+            } else {
+                out = CO[k][j + 1] - CL[k][j + 1];
+                if (j == D - 2) out -= CE[k][j + 1] * mu * gD;
+            }
+            if (j == 0) {
+                in = CO[k][0] + c * CL[k][0];
+            } else {
+                in = CO[k][j] - CL[k][j];
+                if (j == 1) in -= CE[k][1] * c * CL[k][0];
+            }
+            acc += sc_hw(k) * (out + in);
         }
-        if (dmax <= s.sc_tol) break;
+        Ld[j] = acc;
     }
-    return it;
 }
 
-__device__ inline void dev_flux_scatter(const StarDev& s, int i) {
-    if (i >= s.N) return;
-    const ScPixel p = sc_pixel(s, i);
-    for (int b = 0; b < 2; ++b) {
-        sc_setup(s, i, b, p);
-        const int it = sc_iterate(s, i, b);
-        if (s.sc_iters) s.sc_iters[b * s.Npad + i] = it;
-        const double F = sc_flux(s.D, sc_bcol(s, b, SC_TAU, i), sc_bcol(s, b, SC_S, i));
+// Jm = w_m/2 (I+ + I-) along direction m (one third of J = Lambda S)
+__device__ inline void sc_lambda_mu(int D, const Col& tau, const Col& S, const Col& Jm, int m, const Col& CE,
+                                    const Col& CO, const Col& CL) {
+    const double mu = sc_mu(m), hw = sc_hw(m);
+    double I;
+    {
+        const double t0 = tau[0], S0 = S[0];
+        const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+        I = S0 * CO[0] + (S_top - S0) * CL[0];
+        Jm[0] = hw * I;
+    }
+    double Sa = S[0];
+    for (int j = 1; j < D; ++j) {
+        const double Sb = S[j];
+        I = I * CE[j] + Sb * CO[j] + (Sa - Sb) * CL[j];
+        Jm[j] = hw * I;
+        Sa = Sb;
+    }
+    const double SD = S[D - 1];
+    I = SD + mu * (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
+    Jm[D - 1] += hw * I;
+    double Sb = SD;
+    for (int j = D - 2; j >= 0; --j) {
+        const double Sj = S[j];
+        I = I * CE[j + 1] + Sj * CO[j + 1] + (Sb - Sj) * CL[j + 1];
+        Jm[j] += hw * I;
+        Sb = Sj;
+    }
+}
+
+// 2 pi w_m mu_m I+(0, mu_m) of S
+__device__ inline double sc_flux_mu(int D, const Col& tau, const Col& S, int m, const Col& CE, const Col& CO,
+                                    const Col& CL) {
+    const double mu = sc_mu(m);
+    const double SD = S[D - 1];
+    double I = SD + mu * (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
+    double Sb = SD;
+    for (int j = D - 2; j >= 0; --j) {
+        const double Sj = S[j];
+        I = I * CE[j + 1] + Sj * CO[j + 1] + (Sb - Sj) * CL[j + 1];
+        Sb = Sj;
+    }
+    const double t0 = tau[0], S0 = S[0];
+    const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+    return 2.0 * PI * 2.0 * sc_hw(m) * mu * (I * CE[0] + S_top * CO[0] + (S0 - S_top) * CL[0]);
+}
+
+// Forward of one branch for 64 pixels: a workgroup of 64 x 3 threads,
+// threadIdx.y = m the ray direction (called by every thread: it synchronises
+// the workgroup).  Each iteration every direction sweeps into its part of J;
+// then each thread updates the depths j = m (mod 3) of its pixel.  A pixel
+// stops at max_j |dS_j / S_j| <= tol or the cap and its S is then frozen, so
+// its result does not depend on the other pixels of the workgroup.
+__device__ inline void dev_flux_scatter(const StarDev& s, int i, int b) {
+    __shared__ double red[3][64];
+    __shared__ int done[64];
+    const int tx = threadIdx.x, m = threadIdx.y, D = s.D;
+    const bool px = i < s.N;
+    const Col tau = sc_bcol(s, b, SC_TAU, i), eps = sc_bcol(s, b, SC_EPS, i), S = sc_bcol(s, b, SC_S, i),
+              Ld = sc_bcol(s, b, SC_LD, i), B = sc_bcol(s, b, SC_B, i);
+    const Col Jm[3] = {sc_bcol(s, b, SC_JM, i), sc_bcol(s, b, SC_JM + 1, i), sc_bcol(s, b, SC_JM + 2, i)};
+    const Col CE[3] = {sc_bcol(s, b, SC_CE, i), sc_bcol(s, b, SC_CE + 1, i), sc_bcol(s, b, SC_CE + 2, i)};
+    const Col CO[3] = {sc_bcol(s, b, SC_CO, i), sc_bcol(s, b, SC_CO + 1, i), sc_bcol(s, b, SC_CO + 2, i)};
+    const Col CL[3] = {sc_bcol(s, b, SC_CL, i), sc_bcol(s, b, SC_CL + 1, i), sc_bcol(s, b, SC_CL + 2, i)};
+    if (px && m == 0) sc_setup(s, i, b, sc_pixel(s, i));
+    if (m == 0) done[tx] = px ? 0 : 1;
+    __syncthreads();
+    if (px) sc_coeffs(D, tau, m, CE[m], CO[m], CL[m]);
+    __syncthreads();
+    if (px) sc_lambda_diag_part(D, tau, Ld, m, CE, CO, CL);
+    int it = 0;
+    for (;;) {
+        const bool active = px && !done[tx];
+        if (active) sc_lambda_mu(D, tau, S, Jm[m], m, CE[m], CO[m], CL[m]);
+        __syncthreads();
+        double dmax = 0.0;
+        if (active) {
+            for (int j = m; j < D; j += 3) {
+                const double e = eps[j], Sj = S[j];
+                const double J = Jm[0][j] + Jm[1][j] + Jm[2][j];
+                const double Sn = Sj + (e * B[j] + (1.0 - e) * J - Sj) / (1.0 - (1.0 - e) * Ld[j]);
+                dmax = fmax(dmax, fabs(Sn - Sj) / fabs(Sn));
+                S[j] = Sn;
+            }
+        }
+        red[m][tx] = dmax;
+        ++it;
+        __syncthreads();
+        if (m == 0 && active) {
+            const double d = fmax(red[0][tx], fmax(red[1][tx], red[2][tx]));
+            if (d <= s.sc_tol || it >= s.sc_max_iter) {
+                done[tx] = 1;
+                if (s.sc_iters) s.sc_iters[b * s.Npad + i] = it;
+            }
+        }
+        __syncthreads();
+        if (!__syncthreads_or(!done[tx])) break;
+    }
+    const double f = px ? sc_flux_mu(D, tau, S, m, CE[m], CO[m], CL[m]) : 0.0;
+    red[m][tx] = f;
+    __syncthreads();
+    if (px && m == 0) {
         float* out = b == 0 ? s.F : s.Fc;
-        if (out) out[i] = (float)F;
+        if (out) out[i] = (float)(red[0][tx] + red[1][tx] + red[2][tx]);
     }
 }
 
@@ -483,7 +544,7 @@ __device__ inline void dev_reverse_scatter(const StarDev& s, int i) {
     if (i >= s.N) return;
     const int D = s.D;
     const ScPixel p = sc_pixel(s, i);
-    const Col B = sc_col(s, SC_B, i), tau = sc_bcol(s, 0, SC_TAU, i), eps = sc_bcol(s, 0, SC_EPS, i),
+    const Col B = sc_bcol(s, 0, SC_B, i), tau = sc_bcol(s, 0, SC_TAU, i), eps = sc_bcol(s, 0, SC_EPS, i),
               S = sc_bcol(s, 0, SC_S, i), J = sc_bcol(s, 0, SC_J, i), Ld = sc_bcol(s, 0, SC_LD, i);
     const Col lam = sc_col(s, SC_LAM, i), rhs = sc_col(s, SC_RHS, i), gt = sc_col(s, SC_GT, i);
     const Col U = sc_bcol(s, 1, SC_S, i), T = sc_bcol(s, 1, SC_J, i);   // continuum-branch columns as scratch
