@@ -217,13 +217,13 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
                  o_tf = take((size_t)n_tiles * 4), o_tl = take((size_t)n_tiles * 4),
                  o_spo = take((size_t)(S + 1) * 4), o_spi = take(Ls * 4), o_pop = take((size_t)S * 2 * D * 8),
                  o_sdv = take((size_t)S * D * 8), o_lc = take(Ls * 32), o_zmax = take(Ls * D * 4),
-                 o_xlim = take(Ls * 4), o_ikc = take(Ls * 8),
+                 o_xlim = take(Ls * 4), o_wide = take(Ls * 4), o_ikc = take(Ls * 8),
                  o_lp = take(Ls * D * 16), o_kap = take((size_t)D * Npad * 4), o_gk = take((size_t)D * Npad * 4),
                  o_gl = take(Ls * 5 * 4);
     const int n_rchunk = (int)((Ls + RCHUNK - 1) / RCHUNK);
     const size_t o_part = take((size_t)(S + 1) * n_rchunk * 4);
     const size_t o_seed = take((size_t)Npad * 4);
-    const size_t o_order = take((size_t)n_tiles * 4), o_qctr = take(4);
+    const size_t o_order = take((size_t)n_tiles * 4), o_qctr = take(4), o_wany = take(4);
     const bool scatter_ws = (opts->flags & PZ_FLAG_SCATTERING) != 0;
     const size_t o_sc = scatter_ws ? take((size_t)SC_WS_ARRAYS * D * Npad * 8) : 0;
     const size_t o_sci = scatter_ws ? take((size_t)3 * Npad * 4) : 0;
@@ -290,6 +290,8 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->lc = (double4*)(base + o_lc);
     p->zmax = (float*)(base + o_zmax);
     p->xlim = (float*)(base + o_xlim);
+    p->wide_a = (int*)(base + o_wide);
+    p->wide_any = (int*)(base + o_wany);
     p->inv_kcl = (double*)(base + o_ikc);
     p->center_eta = opts->center_eta;
     p->families = (opts->flags & PZ_FLAG_DAMPING_FAMILIES) != 0;
@@ -496,6 +498,8 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.lc = p->lc;
     s.zmax = p->zmax;
     s.xlim = p->xlim;
+    s.wide_a = p->wide_a;
+    s.wide_any = p->wide_any;
     s.inv_kcl = p->inv_kcl;
     s.center_eta = p->center_eta;
     s.center = p->center_eta > 0.0;

@@ -100,7 +100,20 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const St
         if (it >= n) return;
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, false>(s, w.y, s.chunk, sm);
+    }
+}
+
+// Adds the lines flagged wide_a (usually none) to every (star, tile) item.
+template <int WPX>
+__global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity_wide(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
+    __shared__ OpacityLds<WPX> sm;
+    load_pw_table(sm.pw, false);
+    __syncthreads();
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 w = uniform_item(items, it);
+        const StarDev& s = stars[w.x];
+        dev_opacity_tile<WPX, true>(s, w.y, s.chunk, sm);
     }
 }
 
@@ -360,13 +373,19 @@ int synth_batch(const pz_batch* bt, int32_t mode, pz_stream stream) {
     kb_pop<<<grid(bt->grid512, n[PH_POP]), 512, 0, st>>>(bt->stars, it[PH_POP], n[PH_POP]);
     if (n[PH_LINES]) kb_lines<<<grid(bt->grid512, n[PH_LINES]), 512, 0, st>>>(bt->stars, it[PH_LINES], n[PH_LINES]);
     kb_params<<<grid(bt->grid512, n[PH_PARAMS]), 512, 0, st>>>(bt->stars, it[PH_PARAMS], n[PH_PARAMS]);
-    if (n[PH_OP32])
+    if (n[PH_OP32]) {
         kb_opacity<4><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32], bt->ctr);
-    if (n[PH_OP64])
+        kb_opacity_wide<4><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32]);
+    }
+    if (n[PH_OP64]) {
         kb_opacity<8><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64], bt->ctr + 1);
-    if (n[PH_OP128])
+        kb_opacity_wide<8><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64]);
+    }
+    if (n[PH_OP128]) {
         kb_opacity<16><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128], n[PH_OP128],
                                                                           bt->ctr + 2);
+        kb_opacity_wide<16><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128], n[PH_OP128]);
+    }
     kb_flux<<<grid(bt->grid512, n[PH_FLUX]), 512, 0, st>>>(bt->stars, it[PH_FLUX], n[PH_FLUX]);
     if (n[PH_SEED])
         kb_seed<<<grid(bt->grid512, n[PH_SEED]), 512, 0, st>>>(bt->stars, it[PH_SEED], n[PH_SEED], bt->inv_s2, bt->ys);

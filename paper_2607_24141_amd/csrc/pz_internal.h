@@ -87,6 +87,8 @@ struct StarDev {
     double4* lc;                 // [L] per-line factors of K and a (see dev_line_consts)
     float* zmax;                 // [L][D] centre test: kept pairs deposit where v^2 + a^2 <= zmax (-1: dropped)
     float* xlim;                 // [L] centre test: largest |x| any depth of the line reaches (0: none)
+    int* wide_a;                 // [L] 1 if the line's damping ratio spans the near and far wing tiers
+    int* wide_any;               // [1] nonzero if any line is flagged (reset by the populations stage)
     double* inv_kcl;             // [L] centre test: 1 / kappa_c at the line centre
     double center_eta;           // centre-test threshold (0: plain windowed sum)
     bool center;
@@ -140,6 +142,8 @@ struct pz_plan {
     double4* lc;
     float* zmax;
     float* xlim;
+    int* wide_a;
+    int* wide_any;
     double* inv_kcl;
     double center_eta;
     bool families;

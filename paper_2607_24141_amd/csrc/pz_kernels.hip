@@ -34,8 +34,18 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
         const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= s.n_tiles) return;
-        dev_opacity_tile<WPX>(s, s.tile_order[it], chunk, sm);
+        dev_opacity_tile<WPX, false>(s, s.tile_order[it], chunk, sm);
     }
+}
+
+// Adds the lines flagged wide_a (usually none) to the tiles they overlap.
+template <int WPX>
+__global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity_wide(StarDev s, int chunk) {
+    __shared__ OpacityLds<WPX> sm;
+    if (s.wide_any[0] == 0) return;                   // the usual case: no flagged line
+    load_pw_table(sm.pw, false);
+    __syncthreads();
+    for (int t = blockIdx.x; t < s.n_tiles; t += gridDim.x) dev_opacity_tile<WPX, true>(s, t, chunk, sm);
 }
 
 __global__ void k_reset_queue(int* ctr) { ctr[0] = 0; }
@@ -178,9 +188,18 @@ hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
     const int grid = std::max(1, std::min(s.grid_opacity, s.n_tiles));
     k_reset_queue<<<1, 1, 0, st>>>(s.qctr);
     switch (s.tile_px) {
-        case 32: k_opacity<4><<<grid, 512, 0, st>>>(s, chunk); break;
-        case 64: k_opacity<8><<<grid, 512, 0, st>>>(s, chunk); break;
-        case 128: k_opacity<16><<<grid, 512, 0, st>>>(s, chunk); break;
+        case 32:
+            k_opacity<4><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity_wide<4><<<grid, 512, 0, st>>>(s, chunk);
+            break;
+        case 64:
+            k_opacity<8><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity_wide<8><<<grid, 512, 0, st>>>(s, chunk);
+            break;
+        case 128:
+            k_opacity<16><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity_wide<16><<<grid, 512, 0, st>>>(s, chunk);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -51,7 +51,7 @@ struct OpacityLds {
 // With the centre test (CT) a pixel's detuning is marked kNoLine beyond the
 // line's largest span, and a (pixel, depth) lane evaluates only where
 // v^2 + a^2 <= zmax of its (line, depth).
-template <int WPX, bool CT>
+template <int WPX, bool CT, bool WIDE>
 __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
     constexpr int NDG = 64 / WPX;
     constexpr int DPT = MAXD / NDG;                    // most full depth groups
@@ -69,6 +69,13 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
     const int tj = nfull * NDG + (tail ? t - tpx * r : 0);
     const int p0 = tile * TPX;
     const int l0 = s.tile_first[tile], l1 = s.tile_last[tile];
+    const bool any_wide = s.wide_any[0] != 0;
+    if (WIDE && !any_wide) return;
+    if (WIDE) {                                        // nothing to add unless a line of the tile is flagged
+        int any = 0;
+        for (int l = l0 + tid; l < l1; l += 512) any |= s.wide_a[l];
+        if (!__syncthreads_or(any)) return;
+    }
     float acc[DPT], acc_t = 0.0f;
 #pragma unroll
     for (int d = 0; d < DPT; ++d) acc[d] = 0.0f;
@@ -85,7 +92,8 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
             const int q = k / TPX, i = p0 + (k - q * TPX);
             const int l = c0 + q;
             float x = kNoLine;
-            if (i >= s.ln.ilo[l] && i <= s.ln.ihi[l]) x = detuning(i - s.ln.ic[l], s.ln.delta[l], s.h_hi, s.h_lo);
+            if (i >= s.ln.ilo[l] && i <= s.ln.ihi[l] && (any_wide && s.wide_a[l] != 0) == WIDE)
+                x = detuning(i - s.ln.ic[l], s.ln.delta[l], s.h_hi, s.h_lo);
             // the slack keeps every lane the per-depth test would accept
             if (CT && !(fabsf(x) <= s.xlim[l] * (1.0f + 1e-5f))) x = kNoLine;
             sm.x[k] = x;
@@ -100,7 +108,8 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
                 for (int d = 0; d < DPT; ++d) {
                     if (d < nfull) {
                         const float4 p = row[d * NDG + dg];
-                        acc[d] = voigt_acc<CT>(acc[d], p.y, p.z, p.w, x * p.x, sm.pw, CT ? zrow[d * NDG + dg] : 0.0f);
+                        acc[d] = voigt_acc<CT, WIDE>(acc[d], p.y, p.z, p.w, x * p.x, sm.pw,
+                                                     CT ? zrow[d * NDG + dg] : 0.0f);
                     }
                 }
             }
@@ -108,7 +117,7 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
                 const float xt = sm.x[q * TPX + tpx];
                 if (xt < 1.0f) {
                     const float4 p = row[tj];
-                    acc_t = voigt_acc<CT>(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw, CT ? zrow[tj] : 0.0f);
+                    acc_t = voigt_acc<CT, WIDE>(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw, CT ? zrow[tj] : 0.0f);
                 }
             }
         }
@@ -118,19 +127,29 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
     if (i < s.N) {
 #pragma unroll
         for (int d = 0; d < DPT; ++d)
-            if (d < nfull) s.kappa[(size_t)(d * NDG + dg) * s.Npad + i] = acc[d];
+            if (d < nfull) {
+                float* k = s.kappa + (size_t)(d * NDG + dg) * s.Npad + i;
+                *k = WIDE ? *k + acc[d] : acc[d];
+            }
     }
-    if (tail && p0 + tpx < s.N) s.kappa[(size_t)tj * s.Npad + p0 + tpx] = acc_t;
+    if (tail && p0 + tpx < s.N) {
+        float* k = s.kappa + (size_t)tj * s.Npad + p0 + tpx;
+        *k = WIDE ? *k + acc_t : acc_t;
+    }
 }
 
 // Called by all 512 threads of a workgroup (it synchronises the workgroup);
-// sm.pw must hold the piecewise core table.
-template <int WPX>
+// sm.pw must hold the piecewise core table.  The main pass (WIDE = false)
+// writes the tile's opacity from every line not flagged wide_a; the wide
+// pass then adds the flagged lines (whose damping ratio spans both near and
+// far wing tiers across depths) with the evaluator that keeps each lane on
+// its own tier, so the main pass's code stays as lean as before.
+template <int WPX, bool WIDE>
 __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
     if (s.center)
-        opacity_tile_body<WPX, true>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, true, WIDE>(s, tile, chunk, sm);
     else
-        opacity_tile_body<WPX, false>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, false, WIDE>(s, tile, chunk, sm);
 }
 
 }  // namespace pz

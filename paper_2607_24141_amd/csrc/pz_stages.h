@@ -19,6 +19,7 @@ static constexpr int WAVE = 64;
 //   f_I = 1/(1+Phi), f_II = Phi/(1+Phi); infinite chi => single stage.
 // Output n_{s,r}/(rho U_{s,r}) with the abundance correction 10^dA (Eq. 30).
 __device__ __forceinline__ void dev_populations(const StarDev& s, int idx) {
+    if (idx == 0) s.wide_any[0] = 0;                  // raised by dev_line_consts
     if (idx >= s.S * s.D) return;
     const int sp = idx / s.D, j = idx - sp * s.D;
     const double T = s.T[j];
@@ -96,6 +97,19 @@ __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
                            damp * exp10(s.ln.lgr[l] + (df ? (double)df[caller] : 0.0)),
                            damp * exp10(s.ln.lgs[l] + (df ? (double)df[s.L + caller] : 0.0)),
                            damp * exp10(s.ln.lgw[l] + (df ? (double)df[2 * s.L + caller] : 0.0)));
+    {   // damping-ratio range over depth: flags lines whose wavefronts can mix near and far wing tiers
+        const double4 c = s.lc[l];
+        const int sp = s.ln.spion[l] >> 1;
+        double amin = 1e300, amax = 0.0;
+        for (int j = 0; j < s.D; ++j) {
+            const double a = fma(c.w, s.npert[j], fma(c.z, s.ne[j], c.y)) / s.sdv[sp * s.D + j];
+            amin = fmin(amin, a);
+            amax = fmax(amax, a);
+        }
+        const bool wide = (amin < 8.0 && amax > 1.0e3) || (amin < 40.0 && amax > 3.0e4);
+        s.wide_a[l] = wide ? 1 : 0;
+        if (wide) atomicOr(s.wide_any, 1);
+    }
     if (s.center) {
         s.xlim[l] = 0.0f;                                // raised by dev_line_params
         s.inv_kcl[l] = 1.0 / (s.kappa0 * pow(lam * 1.0e7 / s.lam_ref_nm, s.alpha));   // 1 / kappa_c(lambda_l)

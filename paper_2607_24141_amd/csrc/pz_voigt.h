@@ -37,9 +37,10 @@ static constexpr float kInvSqrtPiF = 0.5641895835f;
 //   N_k = z2 + C_k,   D_k = (u - a^2 - C_k)^2 + 4 u a^2 = (z2 - C_k)^2 + 4 C_k a^2,
 // both sums of non-negative terms.  S = sum_k W_k N_k / D_k (H = a S) is
 // summed over the common denominator prod_k D_k, so one reciprocal serves all
-// pairs; no cancellation.  In the wing D_k <= (z2 + C_k)^2, and the callers
-// use NP = 3 only for |z| < 8 and NP = 2 only for |z| < 40 or inside a
-// wavefront that also holds a core lane, far from float32 overflow.
+// pairs; no cancellation.  In the wing D_k <= (z2 + C_k)^2: the products
+// overflow float32 beyond |z| ~ 1600 (NP = 3) and ~ 6e4 (NP = 2), which a
+// wavefront taking those tiers reaches only for lines flagged SAFE (see
+// voigt_acc); those lanes then use their own tier.
 template <int NP>
 __device__ __forceinline__ float wing_S(float a2, float z2, const float* T2, const float* W) {
     float e = z2 - T2[0];
@@ -198,17 +199,29 @@ __device__ __forceinline__ void core_w(double a, double v, double& wr, double& w
 
 // acc + K H(a, v); pw is the piecewise core table in LDS.  With CT the
 // lane adds nothing unless v^2 + a^2 <= zmax2 (centre-test span).
-template <bool CT>
+// SAFE (chosen per line, wavefront-uniform): lanes far out beside near ones,
+// which happen only for lines whose damping ratio spans both the 6- or
+// 4-node range and the far wing across depths, take their own tier, so the
+// pair products of the 6- and 4-node sums stay inside the float32 range.
+template <bool CT, bool SAFE>
 __device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float Ka, float v, const float4* pw,
                                            float zmax2) {
     const float z2 = fmaf(v, v, a2);
     if (CT && !(z2 <= zmax2)) return acc;
     if (__all(z2 >= PZ_VOIGT_TIER2_R2)) {
+        if (SAFE) {
+            const unsigned long long near = __ballot(z2 < PZ_VOIGT_TIER3_R2);
+            if (near != 0 && near != __ballot(1)) {
+                if (z2 < PZ_VOIGT_TIER3_R2) return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
+                return fmaf(Ka, wing_S<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W), acc);
+            }
+        }
         if (__any(z2 < PZ_VOIGT_TIER3_R2)) return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
         return fmaf(Ka, wing_S<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W), acc);
     }
-    if (!__any(z2 < PZ_VOIGT_WING_R2)) return fmaf(Ka, wing_S<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W), acc);
-    // a wavefront with at least one core lane
+    if (!__any(z2 < PZ_VOIGT_WING_R2) && !(SAFE && __any(z2 >= PZ_VOIGT_TIER3_R2)))
+        return fmaf(Ka, wing_S<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W), acc);
+    // a wavefront with at least one core lane (or, SAFE, a far lane)
     if (z2 < PZ_VOIGT_WING_R2) {
         if (a2 <= PZ_VOIGT_A2_SMALL) {
             if (__any(a2 > PZ_VOIGT_A2_TINY)) return coreP_KH_acc<true>(acc, a2, K, Ka, v, pw);
@@ -219,6 +232,7 @@ __device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float K
         return (float)fma((double)K, wr, (double)acc);
     }
     if (z2 < PZ_VOIGT_TIER2_R2) return fmaf(Ka, wing_S<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W), acc);
+    if (SAFE && z2 >= PZ_VOIGT_TIER3_R2) return fmaf(Ka, wing_S<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W), acc);
     return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
 }
 

@@ -1,9 +1,13 @@
 """Edge cases of the synthesis path on the GPU through the C ABI, against the
 FP64 oracle: the smallest grid and atmosphere the ABI accepts (N = 2, D = 2,
 one line), the largest depth count (D = 80), strongly damped lines (a from
-0.01 to several thousand: the float64 core and the large-a wings), 200
-identical lines in one tile (many LDS chunks), and the backward of an empty
-catalogue (zero abundance and microturbulence gradients)."""
+0.01 to several thousand: the float64 core and the large-a wings), a jump of
+the perturber density between adjacent layers (a from ~1 to ~3e4 inside one
+wavefront), 200 identical lines in one tile (many LDS chunks), and the
+backward of an empty catalogue (zero abundance and microturbulence
+gradients)."""
+import copy
+
 import numpy as np
 import pytest
 import torch
@@ -67,6 +71,24 @@ def test_strongly_damped_lines(gpu_lib):
     F, Fc = _run_forward(gpu_lib, wl)
     _flux_close(F, Fc, *O.synthesize(wl))
     _check_vjp(gpu_lib, wl, 71)
+
+
+def test_damping_jump_between_layers(gpu_lib):
+    """n_pert x 100 from layer 8 down: the damping ratio runs from ~1 to ~3e4
+    within one 16-depth group of the opacity kernel, so near and far lanes
+    share a wavefront; each must use a Voigt tier valid for it."""
+    wl = W.tiny(seed=76, L=6, N=300, D=24, S=3)
+    wl.atm = copy.deepcopy(wl.atm)
+    wl.atm.npert[8:] *= 1e2
+    wl.lines.log_gvdw[:] = -3.0
+    wl.lines.log_gstark[:] = -12.0
+    wl.lines.log_grad[:] = 5.0
+    got = _kappa(gpu_lib, wl)
+    ref = O.line_opacity(wl, wl.params)
+    kc = O.continuum_opacity(wl)[None, :]
+    err = np.abs(got - ref) / (ref + 1e-6 * kc)
+    print("damping jump: max kappa err %.3e" % err.max(), flush=True)
+    assert np.all(np.isfinite(got)) and err.max() <= 2e-5
 
 
 def test_identical_lines_pile_up(gpu_lib):
