@@ -136,7 +136,7 @@ def main():
     torch.cuda.set_device(0)
     dev = "cuda"
     log("generating 1500-1700 nm workload")
-    wl = W.config4()
+    wl = W.giant_1500_1700nm_fit()
     atm = pz.Atmos(wl.atm)
     par = pz.Params.from_host(wl.params)
     plan = pz.plan_tuned(wl, atm, par)
@@ -405,7 +405,7 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cb = cpu_baseline(W.config2())
+        cb = cpu_baseline(W.giant_1500_1700nm())
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 

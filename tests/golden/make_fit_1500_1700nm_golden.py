@@ -1,4 +1,4 @@
-"""Writes config4_golden.npz: FP64 oracle reference for differentiating the
+"""Writes fit_1500_1700nm_golden.npz: FP64 oracle reference for differentiating the
 1500-1700 nm workload (37,550 pixels, 2e5 lines, 20 species) through a chi^2
 loss at S/N = 100 (Sec. 5 objective, Eq. 9 ratio, Eq. 30 corrections).
 
@@ -15,7 +15,7 @@ Calls only oracle/ and workloads/.  Contents:
 The adjoint is evaluated with the float32 seed (as a float64 copy), exactly the
 input the GPU test passes to synth_backward.
 
-Usage: python tests/golden/make_config4_golden.py [--procs 8]   (about 15 min on 8 cores)
+Usage: python tests/golden/make_fit_1500_1700nm_golden.py [--procs 8]   (about 15 min on 8 cores)
 """
 import argparse
 import copy
@@ -37,7 +37,7 @@ WL = None
 
 def _init():
     global WL
-    WL = W.config4()
+    WL = W.giant_1500_1700nm_fit()
 
 
 def _fwd(args):
@@ -67,7 +67,7 @@ def loss_of(F, Fc, y, sigma):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--procs", type=int, default=8)
-    ap.add_argument("--out", default=os.path.join(HERE, "config4_golden.npz"))
+    ap.add_argument("--out", default=os.path.join(HERE, "fit_1500_1700nm_golden.npz"))
     args = ap.parse_args()
     t0 = time.time()
     _init()

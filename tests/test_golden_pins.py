@@ -1,6 +1,6 @@
 """Pins of the stored FP64 oracle reference for the 1500-1700 nm
-differentiation workload (tests/golden/config4_golden.npz, written by
-tests/golden/make_config4_golden.py from the oracle alone).
+differentiation workload (tests/golden/fit_1500_1700nm_golden.npz, written by
+tests/golden/make_fit_1500_1700nm_golden.py from the oracle alone).
 
 * The stored oracle adjoint agrees with FP64 central differences of the
   oracle's own forward synthesis (Richardson-combined steps h and h/2) for
@@ -20,7 +20,7 @@ import pytest
 import workloads as W
 from oracle import synth as O
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config4_golden.npz")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fit_1500_1700nm_golden.npz")
 
 
 @pytest.fixture(scope="module")
@@ -52,7 +52,7 @@ def test_adjoint_matches_finite_differences(golden):
 
 def test_target_and_seed_reproduce(golden):
     z = golden
-    wl = W.config4()
+    wl = W.giant_1500_1700nm_fit()
     rng = np.random.default_rng(5)
     pix = np.unique(np.concatenate([[0, wl.grid.N - 1], rng.integers(0, wl.grid.N, 14)]))
     Ft, Fct = O.synthesize(wl, wl.extra["truth"], pix=pix)

@@ -162,7 +162,7 @@ def test_reverse_scan_vs_oracle(gpu_lib, seed, L, N, D, quad):
 
 def test_reverse_scan_1500_1700nm_sampled(gpu_lib):
     pz = gpu_lib
-    wl = W.config2()
+    wl = W.giant_1500_1700nm()
     rng = np.random.default_rng(3)
     s = rng.normal(size=wl.grid.N).astype(np.float32)
     plan = pz.plan_for(wl)

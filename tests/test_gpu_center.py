@@ -59,7 +59,7 @@ def test_center_opacity_vs_oracle(gpu_lib):
 
 
 def test_center_1500_1700nm_sampled(gpu_lib):
-    wl = W.config2()
+    wl = W.giant_1500_1700nm()
     wl.center_eta = 1e-3
     F, Fc = _run_forward(gpu_lib, wl)
     pix = _sample_pixels(wl.grid.N, np.random.default_rng(11), n=48)

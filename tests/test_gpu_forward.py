@@ -59,7 +59,7 @@ def test_line_opacity_tiny(gpu_lib, seed, L, N, D, tile):
 
 def test_flux_500_503nm_full(gpu_lib):
     """1,795-pixel, 1,000-line solar case: every pixel vs the oracle."""
-    wl = W.config1()
+    wl = W.solar_500_503nm()
     F, Fc = _run_forward(gpu_lib, wl)
     Fo, Fco = O.synthesize(wl)
     print("max rel f err", _flux_close(F, Fc, Fo, Fco))
@@ -143,7 +143,7 @@ def test_formal_solution_curved_source(gpu_lib):
 
 def test_flux_500_503nm_e2(gpu_lib):
     """The E2 form of Eq. 8 on the 500-503 nm case, every pixel vs the oracle."""
-    wl = W.config1()
+    wl = W.solar_500_503nm()
     wl.quadrature = "e2"
     F, Fc = _run_forward(gpu_lib, wl)
     Fo, Fco = O.synthesize(wl)
@@ -158,7 +158,7 @@ def _sample_pixels(N, rng, n=96, tile=64):
 
 def test_flux_1500_1700nm_sampled(gpu_lib):
     """37,550 pixels, 2e5 lines (30% in bands): sampled pixels vs the oracle."""
-    wl = W.config2()
+    wl = W.giant_1500_1700nm()
     F, Fc = _run_forward(gpu_lib, wl)
     pix = _sample_pixels(wl.grid.N, np.random.default_rng(0))
     Fo, Fco = O.synthesize(wl, pix=pix)
@@ -168,7 +168,7 @@ def test_flux_1500_1700nm_sampled(gpu_lib):
 
 def test_flux_300_1000nm_sampled(gpu_lib):
     """361,193 pixels, 5e6 lines with density ~ lambda^-2: sampled pixels vs the oracle."""
-    wl = W.config3()
+    wl = W.solar_300_1000nm()
     F, Fc = _run_forward(gpu_lib, wl)
     rng = np.random.default_rng(1)
     pix = np.unique(np.concatenate([_sample_pixels(wl.grid.N, rng, n=24), rng.integers(0, 3000, 8)]))

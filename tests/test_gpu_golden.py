@@ -1,7 +1,7 @@
 """Full-size gradient parity on the differentiation workload (1500-1700 nm,
 37,550 pixels, 2e5 lines, 20 species), through the C ABI, against FP64 oracle
-values stored in tests/golden/config4_golden.npz (written by
-tests/golden/make_config4_golden.py, which calls only the oracle).
+values stored in tests/golden/fit_1500_1700nm_golden.npz (written by
+tests/golden/make_fit_1500_1700nm_golden.py, which calls only the oracle).
 
 The chi^2 objective (Sec. 5, Eq. 9 flux ratio) is evaluated at the base
 corrections against a target made from the truth corrections plus noise at
@@ -17,14 +17,14 @@ import workloads as W
 from test_gpu_adjoint import grad_close_cond
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config4_golden.npz")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fit_1500_1700nm_golden.npz")
 
 
 @pytest.fixture(scope="module")
 def run(gpu_lib):
     pz = gpu_lib
     z = np.load(GOLDEN)
-    wl = W.config4()
+    wl = W.giant_1500_1700nm_fit()
     plan = pz.plan_for(wl)
     atm, par = pz.Atmos(wl.atm), pz.Params.from_host(wl.params)
     N, L, S = plan.N, plan.L, plan.S

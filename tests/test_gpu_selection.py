@@ -64,9 +64,9 @@ def test_keep_test_vs_oracle_small(gpu_lib, seed, eta, bin_ln):
     _compare(wl, _run(gpu_lib, wl, eta, bin_ln), ref, bin_ln)
 
 
-@pytest.mark.parametrize("cfg", [2, 3])
-def test_keep_test_vs_oracle_full_catalogues(gpu_lib, cfg):
-    wl = W.CONFIGS[cfg]()
+@pytest.mark.parametrize("make", [W.giant_1500_1700nm, W.solar_300_1000nm])
+def test_keep_test_vs_oracle_full_catalogues(gpu_lib, make):
+    wl = make()
     wl.params = _f32_params(wl.params)
     ref = OS.select_lines(wl, wl.params, 1e-3, 1e-3)
     _compare(wl, _run(gpu_lib, wl, 1e-3, 1e-3), ref, 1e-3)

@@ -24,8 +24,8 @@ Recipes (all numbers are the workload definitions, not physics of the path):
   log gamma_rad ~ U[7, 9] s^-1, log gamma_S ~ U[-7, -4] and
   log gamma_vdW ~ U[-9, -7] cm^3 s^-1 (Table 1 line and broadening symbols).
 
-Seeds: numpy PCG64 with seed 240000 + config index; star b of the batch
-configuration uses 250000 + b.
+Seeds: numpy PCG64, one fixed seed per workload (240001-240006); star b of the batch
+workload uses 250000 + b.
 """
 from __future__ import annotations
 
@@ -196,7 +196,7 @@ def zero_params(L, S, xi):
     return Params(np.zeros(L), np.zeros(L), np.zeros(S), float(xi))
 
 
-def config1(seed=240_001):
+def solar_500_503nm(seed=240_001):
     """Plain forward: 500-503 nm, R=300,000, solar, 1,000 lines, 10 species."""
     rng = np.random.Generator(np.random.PCG64(seed))
     grid = grid_for(500.0, 503.0, 3.0e5)
@@ -213,7 +213,7 @@ def _apogee_mixture(rng, L, lam_lo, lam_hi, S_atomic, mol_species):
     return concat_lines(atom, bands)
 
 
-def config2(seed=240_002, L=200_000):
+def giant_1500_1700nm(seed=240_002, L=200_000):
     """1500-1700 nm, R=300,000, Arcturus-like giant, 2e5 lines (30% in bands)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     grid = grid_for(1500.0, 1700.0, 3.0e5)
@@ -224,7 +224,7 @@ def config2(seed=240_002, L=200_000):
                     zero_params(lines.L, 20, 1.7))
 
 
-def config3(seed=240_003, L=5_000_000):
+def solar_300_1000nm(seed=240_003, L=5_000_000):
     """300-1000 nm, R=300,000, solar, 5e6 lines with density ~ lambda^-2."""
     rng = np.random.Generator(np.random.PCG64(seed))
     lo, hi = 300.0, 1000.0
@@ -237,9 +237,9 @@ def config3(seed=240_003, L=5_000_000):
     return Workload("300-1000nm_R3e5_L5e6_solar", grid, atm, lines, zero_params(L, 40, 0.7))
 
 
-def config4(seed=240_004):
+def giant_1500_1700nm_fit(seed=240_004):
     """Differentiation on the 1500-1700 nm workload: truth perturbation + noise."""
-    wl = config2()
+    wl = giant_1500_1700nm()
     rng = np.random.Generator(np.random.PCG64(seed))
     L, S = wl.lines.L, wl.atm.S
     truth = Params(rng.normal(0.0, 0.05, L), rng.normal(0.0, 0.1, L), rng.normal(0.0, 0.05, S),
@@ -255,7 +255,7 @@ BATCH_N_MAX = None  # set per star from the 1500-1700 nm interval
 
 
 def batch_star(b, seed_base=250_000, S=20):
-    """Star b of the batched configuration (window and line count drawn per star)."""
+    """Star b of the 256-star batch (window and line count drawn per star)."""
     rng = np.random.Generator(np.random.PCG64(seed_base + b))
     Teff = rng.uniform(3500.0, 7000.0)
     logg = rng.uniform(1.0, 5.0)
@@ -279,7 +279,7 @@ def batch_star(b, seed_base=250_000, S=20):
     return wl
 
 
-def config5(n_star=256):
+def batch_stars(n_star=256):
     return [batch_star(b) for b in range(n_star)]
 
 
@@ -304,7 +304,6 @@ def random_params(rng, L, S, xi, scale=1.0):
                   rng.normal(0.0, 0.05 * scale, S), float(xi))
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 
 def apogee_instrument(grid, R_lsf=(20000.0, 25000.0), vb_max_kms=20.0):
