@@ -216,7 +216,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
                  o_delta = take(Ls * 4), o_ilo = take(Ls * 4), o_ihi = take(Ls * 4), o_perm = take(Ls * 4),
                  o_tf = take((size_t)n_tiles * 4), o_tl = take((size_t)n_tiles * 4),
                  o_spo = take((size_t)(S + 1) * 4), o_spi = take(Ls * 4), o_pop = take((size_t)S * 2 * D * 8),
-                 o_sdv = take((size_t)S * D * 8), o_lc = take(Ls * 32), o_zmax = take(Ls * D * 4),
+                 o_idv = take((size_t)S * D * 8), o_lc = take(Ls * 32), o_zmax = take(Ls * D * 4),
                  o_xlim = take(Ls * 4), o_wide = take(Ls * 4), o_ikc = take(Ls * 8),
                  o_lp = take(Ls * D * 16), o_kap = take((size_t)D * Npad * 4), o_gk = take((size_t)D * Npad * 4),
                  o_gl = take(Ls * 5 * 4);
@@ -286,7 +286,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     p->sp_off = (int*)(base + o_spo);
     p->sp_idx = (int*)(base + o_spi);
     p->pop = (double*)(base + o_pop);
-    p->sdv = (double*)(base + o_sdv);
+    p->inv_dv = (double*)(base + o_idv);
     p->lc = (double4*)(base + o_lc);
     p->zmax = (float*)(base + o_zmax);
     p->xlim = (float*)(base + o_xlim);
@@ -494,7 +494,7 @@ StarDev make_star(const pz_plan* p, const pz_atmos* atm, const pz_params* par) {
     s.dA = par->dA;
     s.xi = par->xi_kms;
     s.pop = p->pop;
-    s.sdv = p->sdv;
+    s.inv_dv = p->inv_dv;
     s.lc = p->lc;
     s.zmax = p->zmax;
     s.xlim = p->xlim;

@@ -75,9 +75,11 @@ __global__ __launch_bounds__(512) void kb_pop(const StarDev* __restrict__ stars,
 }
 
 __global__ __launch_bounds__(512) void kb_lines(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
+    __shared__ double red[3 * 512];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
-        dev_line_consts(stars[w.x], w.y * 512 + threadIdx.x);
+        const double3 bnd = damp_bounds(stars[w.x], red);
+        dev_line_consts(stars[w.x], w.y * 512 + threadIdx.x, bnd);
     }
 }
 

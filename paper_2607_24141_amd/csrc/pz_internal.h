@@ -83,7 +83,7 @@ struct StarDev {
     float* g_xi;
     // plan workspaces
     double* pop;                 // [S][2][D] n/(rho U) including 10^dA
-    double* sdv;                 // [S][D] Doppler velocity width dv (cm/s)
+    double* inv_dv;              // [S][D] 1 / Doppler velocity width dv (s/cm)
     double4* lc;                 // [L] per-line factors of K and a (see dev_line_consts)
     float* zmax;                 // [L][D] centre test: kept pairs deposit where v^2 + a^2 <= zmax (-1: dropped)
     float* xlim;                 // [L] centre test: largest |x| any depth of the line reaches (0: none)
@@ -138,7 +138,7 @@ struct pz_plan {
     int* sp_off;
     int* sp_idx;
     double* pop;
-    double* sdv;
+    double* inv_dv;
     double4* lc;
     float* zmax;
     float* xlim;

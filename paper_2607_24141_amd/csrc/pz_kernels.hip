@@ -13,7 +13,11 @@ __global__ __launch_bounds__(256) void k_populations(StarDev s) {
     dev_populations(s, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_line_consts(StarDev s) { dev_line_consts(s, blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ __launch_bounds__(256) void k_line_consts(StarDev s) {
+    __shared__ double red[3 * 256];
+    const double3 bnd = damp_bounds(s, red);
+    dev_line_consts(s, blockIdx.x * blockDim.x + threadIdx.x, bnd);
+}
 
 __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
     dev_line_params(s, (long)blockIdx.x * blockDim.x + threadIdx.x);

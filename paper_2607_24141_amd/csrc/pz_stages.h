@@ -41,9 +41,9 @@ __device__ __forceinline__ void dev_populations(const StarDev& s, int idx) {
     const double n = (s.dA ? exp10((double)s.dA[sp]) : 1.0) * s.n_species[sp * s.D + j];
     s.pop[(sp * 2 + 0) * s.D + j] = n * fI / (s.rho[j] * U0);
     s.pop[(sp * 2 + 1) * s.D + j] = n * fII / (s.rho[j] * U1);
-    // Doppler width (Eq. 5), per species and depth
+    // reciprocal Doppler width (Eq. 5), per species and depth
     const double xi = (double)s.xi[0] * 1.0e5;
-    s.sdv[sp * s.D + j] = sqrt(2.0 * K_BOLTZ * T / (s.mass[sp] * AMU_G) + xi * xi);
+    s.inv_dv[sp * s.D + j] = 1.0 / sqrt(2.0 * K_BOLTZ * T / (s.mass[sp] * AMU_G) + xi * xi);
 }
 
 // ------------------------------------------------- line-selection keep test
@@ -69,7 +69,7 @@ __device__ __forceinline__ void dev_select(const StarDev& s, int l, double eta, 
     double Q = 0.0;
     for (int j = 0; j < s.D; ++j) {
         const double C = eta * kc / (-expm1(-H_PLANCK * nu_b / (K_BOLTZ * s.T[j])));
-        Q = fmax(Q, s.pop[spion * s.D + j] / (s.sdv[sp * s.D + j] / C_LIGHT * C));
+        Q = fmax(Q, s.pop[spion * s.D + j] * s.inv_dv[sp * s.D + j] * C_LIGHT / C);
     }
     const double loggf = s.ln.loggf[l] + (s.dgf ? (double)s.dgf[caller] : 0.0);
     const double R = sqrt(PI) * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT) * exp10(loggf) * Q / nu_b;
@@ -85,7 +85,34 @@ __device__ __forceinline__ void dev_select(const StarDev& s, int l, double eta, 
 // Per line (Eqs. 4, 5, 30), in float64:
 //   x = (pi e^2/m_e c) 10^(loggf+dgf) lambda_l / sqrt(pi)
 //   y, z, w = 10^ddamp lambda_l / (4 pi) x (g_rad 10^d_rad, g_S 10^d_S, g_vdW 10^d_vdW)
-__device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
+// Block-wide maxima of n_e and n_pert over depth and of 1/dv over (species,
+// depth): with them (g_rad + g_S max n_e + g_vdW max n_pert) max(1/dv) bounds
+// every line's damping ratio a from above.  Every thread of the workgroup
+// calls this (it synchronises); red holds 3 doubles per thread.
+__device__ __forceinline__ double3 damp_bounds(const StarDev& s, double* red) {
+    const int t = threadIdx.x, n = blockDim.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int j = t; j < s.D; j += n) {
+        a = fmax(a, s.ne[j]);
+        b = fmax(b, s.npert[j]);
+    }
+    for (int k = t; k < s.S * s.D; k += n) c = fmax(c, s.inv_dv[k]);
+    red[t] = a;
+    red[n + t] = b;
+    red[2 * n + t] = c;
+    __syncthreads();
+    for (int w = n / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int r = 0; r < 3; ++r) red[r * n + t] = fmax(red[r * n + t], red[r * n + t + w]);
+        __syncthreads();
+    }
+    const double3 out = make_double3(red[0], red[n], red[2 * n]);
+    __syncthreads();
+    return out;
+}
+
+// bnd: damp_bounds of the workgroup.
+__device__ __forceinline__ void dev_line_consts(const StarDev& s, int l, double3 bnd) {
     if (l >= s.L) return;
     const int caller = s.ln.perm[l];
     const double lam = s.ln.lam_cm[l];
@@ -99,14 +126,17 @@ __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l) {
                            damp * exp10(s.ln.lgw[l] + (df ? (double)df[2 * s.L + caller] : 0.0)));
     {   // damping-ratio range over depth: flags lines whose wavefronts can mix near and far wing tiers
         const double4 c = s.lc[l];
-        const int sp = s.ln.spion[l] >> 1;
-        double amin = 1e300, amax = 0.0;
-        for (int j = 0; j < s.D; ++j) {
-            const double a = fma(c.w, s.npert[j], fma(c.z, s.ne[j], c.y)) / s.sdv[sp * s.D + j];
-            amin = fmin(amin, a);
-            amax = fmax(amax, a);
+        bool wide = false;
+        if (fma(c.w, bnd.y, fma(c.z, bnd.x, c.y)) * bnd.z > 1.0e3) {   // else a <= 1000 at every depth
+            const int sp = s.ln.spion[l] >> 1;
+            double amin = 1e300, amax = 0.0;
+            for (int j = 0; j < s.D; ++j) {
+                const double a = fma(c.w, s.npert[j], fma(c.z, s.ne[j], c.y)) * s.inv_dv[sp * s.D + j];
+                amin = fmin(amin, a);
+                amax = fmax(amax, a);
+            }
+            wide = (amin < 8.0 && amax > 1.0e3) || (amin < 40.0 && amax > 3.0e4);
         }
-        const bool wide = (amin < 8.0 && amax > 1.0e3) || (amin < 40.0 && amax > 3.0e4);
         s.wide_a[l] = wide ? 1 : 0;
         if (wide) atomicOr(s.wide_any, 1);
     }
@@ -132,7 +162,7 @@ __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
     const int l = (int)(id / s.D), j = (int)(id - (long)l * s.D);
     const double T = s.T[j];
     const int spion = s.ln.spion[l];
-    const double inv_dv = 1.0 / s.sdv[(spion >> 1) * s.D + j];
+    const double inv_dv = s.inv_dv[(spion >> 1) * s.D + j];
     const double4 c = s.lc[l];
     const double a = fma(c.w, s.npert[j], fma(c.z, s.ne[j], c.y)) * inv_dv;
     const double kT = K_BOLTZ * T;
