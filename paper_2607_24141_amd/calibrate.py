@@ -187,7 +187,7 @@ def fit(cal, theta0=None, bounds=DEFAULT_BOUNDS, max_iter=40, history_size=10, m
     opt.step(closure)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    st = opt.state[opt._params[0]]
+    st = opt.state[u]
     with torch.no_grad():
         theta = bound(u, b).detach()
         loss = float(cal.evaluate(theta.contiguous())[0][0])

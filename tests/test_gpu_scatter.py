@@ -125,3 +125,34 @@ def test_scattering_rejected_where_unsupported(gpu_lib):
     F = torch.empty(wl.grid.N, device="cuda")
     with pytest.raises(pz.PzError):
         pz.synth_forward(plan, pz.Atmos(wl.atm), pz.Params.from_host(wl.params), F, torch.empty_like(F))
+
+
+def test_full_size_sampled(gpu_lib):
+    """The 1500-1700 nm workload (37,550 pixels, 2e5 lines, 72 depths) with grey
+    scattering sigma_c = 0.5 kappa_0, as the bench times it: F, F_c and
+    dL/dkappa_line at sampled pixels against the oracle's per-pixel fixed
+    point and complex-step derivative."""
+    pz = gpu_lib
+    wl = W.giant_1500_1700nm()
+    wl.atm = copy.deepcopy(wl.atm)
+    wl.atm.sigma_c = np.full(wl.atm.D, 0.5 * wl.atm.kappa0)
+    wl.atm.sigma_alpha = 0.0
+    print("scatter full size", flush=True)
+    plan, F, Fc = _forward(pz, wl)
+    rng = np.random.default_rng(11)
+    pix = np.unique(rng.integers(0, wl.grid.N, 24))
+    Fo, Fco = SC.synthesize(wl, None, pix)
+    err = max(np.max(np.abs(F[pix] / Fo - 1)), np.max(np.abs(Fc[pix] / Fco - 1)))
+    print("full size: max rel err %.3e at %d pixels, iterations %s" % (err, pix.size, plan.scatter_iterations()),
+          flush=True)
+    assert err <= 1e-5
+    s = rng.normal(size=wl.grid.N).astype(np.float32)
+    g = torch.empty((wl.atm.D, wl.grid.N), device="cuda")
+    pz.pz_debug_opacity_adjoint(plan, pz.Atmos(wl.atm), pz.Params.from_host(wl.params),
+                                torch.as_tensor(s, device="cuda"), g)
+    torch.cuda.synchronize()
+    ref = SC.opacity_adjoint(wl, O.line_opacity(wl, None, pix), s[pix].astype(np.float64), pix)
+    got = g.cpu().numpy()[:, pix]
+    e = np.abs(got - ref) / np.max(np.abs(ref), axis=0, keepdims=True)
+    print("full size: max rel err of dL/dkappa %.3e" % e.max(), flush=True)
+    assert e.max() <= 2e-5
