@@ -33,7 +33,10 @@ METRIC = "spectra/s, Voigt evals/s: fwd, fwd+bwd, batched vs plain fwd at 1e-4 r
 # (2), a^2, u - a^2, 4 u a^2, u + a^2 (5), three node pairs x (sub, FMA, add, mul,
 # rcp, FMA = 8), a * sum (1), kappa += K H (2).
 FLOPS_PER_EVAL = 34
-PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak (counts packed two-wide FP32)
+# The same chip without packed FP32, which this library's build turns off: 256 CUs x 4 SIMDs
+# x 16 lanes per clock (a wave64 FMA issues over 4 cycles) x 2 flops x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # sources of the opacity kernel: a committed HBM-traffic measurement is used only if they are unchanged
 # The opacity kernel's code: its tile body and the Voigt evaluator, plus the
 # kernel's own definition in pz_kernels.hip (other code in that file is not
@@ -177,7 +180,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_opacity", "achieved": achieved_tflops,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                      "traffic": traffic_from_profiles("opacity"), "kernel_avg_ms": op_avg_ms,
-                     "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": plan.voigt_evals},
+                     "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": plan.voigt_evals,
+                     "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                     "frac_unpacked": achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS},
         "wall_s_timed": wall_fwd,
     }
 
