@@ -33,10 +33,7 @@ METRIC = "spectra/s, Voigt evals/s: fwd, fwd+bwd, batched vs plain fwd at 1e-4 r
 # (2), a^2, u - a^2, 4 u a^2, u + a^2 (5), three node pairs x (sub, FMA, add, mul,
 # rcp, FMA = 8), a * sum (1), kappa += K H (2).
 FLOPS_PER_EVAL = 34
-PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak (counts packed two-wide FP32)
-# The same chip without packed FP32, which this library's build turns off: 256 CUs x 4 SIMDs
-# x 16 lanes per clock (a wave64 FMA issues over 4 cycles) x 2 flops x 2.4 GHz.
-PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 # sources of the opacity kernel: a committed HBM-traffic measurement is used only if they are unchanged
 # The opacity kernel's code: its tile body and the Voigt evaluator, plus the
 # kernel's own definition in pz_kernels.hip (other code in that file is not
@@ -180,9 +177,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_opacity", "achieved": achieved_tflops,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                      "traffic": traffic_from_profiles("opacity"), "kernel_avg_ms": op_avg_ms,
-                     "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": plan.voigt_evals,
-                     "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
-                     "frac_unpacked": achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS},
+                     "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": plan.voigt_evals},
         "wall_s_timed": wall_fwd,
     }
 
@@ -294,13 +289,17 @@ def main():
             pz.pz_chi2_seed(F, Fc, ys, 0.01, gS, None, None)
             pz.synth_backward(splan, satm, par, gS, *gl)
 
+        splan.profile(True)
         ms_sfb, _ = timed(sfb, args.steps, args.warmup, torch)
+        sprof_b = splan.profile_read()
+        splan.profile(False)
         it_b = splan.scatter_iterations()
         out["scattering"] = {"sigma_c_over_kappa_c": 0.5, "fwd_spectra_per_s": 1000.0 / ms_sf, "fwd_ms": ms_sf,
                              "fwd_bwd_spectra_per_s": 1000.0 / ms_sfb, "fwd_bwd_ms": ms_sfb,
                              "flux_stage_ms": sprof["flux"][0] / max(sprof["flux"][1], 1),
                              "max_iterations_fwd": [int(it_f[0]), int(it_f[1])],
-                             "max_iterations_adjoint": int(it_b[2])}
+                             "max_iterations_adjoint": int(it_b[2]),
+                             "stage_ms_fwd_bwd": {k: (v[0] / max(v[1], 1)) for k, v in sprof_b.items() if v[1]}}
         splan.destroy()
 
     # ---- the instrument operator of Eq. 31 on APOGEE-like pixels (one flux pair)

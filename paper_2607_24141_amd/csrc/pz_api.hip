@@ -312,7 +312,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     std::vector<int> torder(n_tiles);
     std::iota(torder.begin(), torder.end(), 0);
     std::stable_sort(torder.begin(), torder.end(), [&](int a, int b) { return tcost[a] > tcost[b]; });
-    p->grid_opacity = opacity_grid(tile_px);
+    p->grid_opacity = opacity_grid(tile_px, opts->center_eta > 0.0);
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };

@@ -92,9 +92,10 @@ __global__ __launch_bounds__(512) void kb_params(const StarDev* __restrict__ sta
     }
 }
 
-template <int WPX>
+// ANYCT: some star of the batch uses the centre test (the LDS holds its rows).
+template <int WPX, bool ANYCT>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
-    __shared__ OpacityLds<WPX> sm;
+    __shared__ OpacityLds<WPX, ANYCT> sm;
     __shared__ int s_it;
     load_pw_table(sm.pw, false);                       // visible after the first item fetch's barrier
     for (;;) {
@@ -102,20 +103,20 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const St
         if (it >= n) return;
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, false>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, false, ANYCT>(s, w.y, s.chunk, sm);
     }
 }
 
 // Adds the lines flagged wide_a (usually none) to every (star, tile) item.
-template <int WPX>
+template <int WPX, bool ANYCT>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity_wide(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
-    __shared__ OpacityLds<WPX> sm;
+    __shared__ OpacityLds<WPX, ANYCT> sm;
     load_pw_table(sm.pw, false);
     __syncthreads();
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, true>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, true, ANYCT>(s, w.y, s.chunk, sm);
     }
 }
 
@@ -123,10 +124,11 @@ __global__ __launch_bounds__(512) void kb_flux(const StarDev* __restrict__ stars
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
+        const int i = w.y * 512 + threadIdx.x;
         if (s.quad == PZ_QUAD_E2)
-            dev_flux_e2(s, w.y * 512 + threadIdx.x);
+            dev_flux_e2(s, i);
         else
-            dev_flux(s, w.y * 512 + threadIdx.x);
+            dev_flux<true, true>(s, i, GlobalKCol{s.kappa + i, (size_t)s.Npad});
     }
 }
 
@@ -152,13 +154,17 @@ __global__ __launch_bounds__(1024) void kb_loss(const StarDev* __restrict__ star
 }
 
 __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
+    __shared__ float kst[MAXD * WAVE];                // each thread's own kappa_line column
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        if (s.quad == PZ_QUAD_E2)
-            dev_reverse_scan_e2<MAXD>(s, w.y * 64 + threadIdx.x);
-        else
-            dev_reverse_scan<MAXD>(s, w.y * 64 + threadIdx.x);
+        const int i = w.y * 64 + threadIdx.x;
+        if (s.quad == PZ_QUAD_E2) {
+            dev_reverse_scan_e2<MAXD>(s, i);
+        } else {
+            if (i < s.N) stage_kappa_column(s, i, kst + threadIdx.x);
+            dev_reverse_scan<MAXD>(s, i, LdsKCol{kst + threadIdx.x});
+        }
     }
 }
 
@@ -217,10 +223,19 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+template <bool ANYCT>
+static hipError_t batch_opacity_occupancy(int* occ) {
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], kb_opacity<4, ANYCT>, 512, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], kb_opacity<8, ANYCT>, 512, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], kb_opacity<16, ANYCT>, 512, 0);
+    return e;
+}
+
 struct pz_batch {
     int n_star;
     int device;
     bool has_target;
+    bool any_center;      // some star uses the centre test
     std::vector<const pz_plan*> plans;
     int n_items[N_PHASE];
     int2* items[N_PHASE];
@@ -232,6 +247,28 @@ struct pz_batch {
     int grid512, grid256, grid1024, grid_op[3], grid_gather, grid_rev;
     void* base;
 };
+
+template <bool ANYCT>
+static void batch_opacity(const pz_batch* bt, hipStream_t st) {
+    auto grid = [](int want, int n) { return std::max(1, std::min(want, n)); };
+    const int* n = bt->n_items;
+    int2* const* it = bt->items;
+    if (n[PH_OP32]) {
+        kb_opacity<4, ANYCT><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32], bt->ctr);
+        kb_opacity_wide<4, ANYCT><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32]);
+    }
+    if (n[PH_OP64]) {
+        kb_opacity<8, ANYCT><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64],
+                                                                             bt->ctr + 1);
+        kb_opacity_wide<8, ANYCT><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64]);
+    }
+    if (n[PH_OP128]) {
+        kb_opacity<16, ANYCT><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128], n[PH_OP128],
+                                                                               bt->ctr + 2);
+        kb_opacity_wide<16, ANYCT><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128],
+                                                                                    n[PH_OP128]);
+    }
+}
 
 extern "C" {
 
@@ -335,9 +372,10 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
     if (e == hipSuccess) e = hipMemcpy(bt->losses, losses.data(), n_star * 8, hipMemcpyHostToDevice);
     int n_cu = 0, occ_op[3] = {0, 0, 0}, occ_g = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, bt->device);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_op[0], kb_opacity<4>, 512, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_op[1], kb_opacity<8>, 512, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_op[2], kb_opacity<16>, 512, 0);
+    bt->any_center = false;
+    for (int b = 0; b < n_star; ++b) bt->any_center = bt->any_center || sd[b].center;
+    if (e == hipSuccess)
+        e = bt->any_center ? batch_opacity_occupancy<true>(occ_op) : batch_opacity_occupancy<false>(occ_op);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_g, kb_gather, 512, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -375,19 +413,10 @@ int synth_batch(const pz_batch* bt, int32_t mode, pz_stream stream) {
     kb_pop<<<grid(bt->grid512, n[PH_POP]), 512, 0, st>>>(bt->stars, it[PH_POP], n[PH_POP]);
     if (n[PH_LINES]) kb_lines<<<grid(bt->grid512, n[PH_LINES]), 512, 0, st>>>(bt->stars, it[PH_LINES], n[PH_LINES]);
     kb_params<<<grid(bt->grid512, n[PH_PARAMS]), 512, 0, st>>>(bt->stars, it[PH_PARAMS], n[PH_PARAMS]);
-    if (n[PH_OP32]) {
-        kb_opacity<4><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32], bt->ctr);
-        kb_opacity_wide<4><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32]);
-    }
-    if (n[PH_OP64]) {
-        kb_opacity<8><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64], bt->ctr + 1);
-        kb_opacity_wide<8><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64]);
-    }
-    if (n[PH_OP128]) {
-        kb_opacity<16><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128], n[PH_OP128],
-                                                                          bt->ctr + 2);
-        kb_opacity_wide<16><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128], n[PH_OP128]);
-    }
+    if (bt->any_center)
+        batch_opacity<true>(bt, st);
+    else
+        batch_opacity<false>(bt, st);
     kb_flux<<<grid(bt->grid512, n[PH_FLUX]), 512, 0, st>>>(bt->stars, it[PH_FLUX], n[PH_FLUX]);
     if (n[PH_SEED])
         kb_seed<<<grid(bt->grid512, n[PH_SEED]), 512, 0, st>>>(bt->stars, it[PH_SEED], n[PH_SEED], bt->inv_s2, bt->ys);

@@ -105,11 +105,11 @@ struct StarDev {
 };
 
 static constexpr int RCHUNK = 2048;      // lines per reduction partial
-static constexpr int SC_WS_ARRAYS = 42;  // [D][Npad] float64 arrays of the scattering workspace
+static constexpr int SC_WS_ARRAYS = 39;  // [D][Npad] float64 arrays of the scattering workspace
 
 // Kernel launchers (pz_kernels.hip).  Each enqueues on the stream and returns
 // the hipError_t of the launch.
-int opacity_grid(int tile_px);   // persistent opacity workgroups for this device
+int opacity_grid(int tile_px, bool center);   // persistent opacity workgroups for this device
 hipError_t launch_populations(const StarDev& s, hipStream_t st);
 hipError_t launch_line_params(const StarDev& s, hipStream_t st);
 hipError_t launch_select(const StarDev& s, double eta, double bin_ln, int B, unsigned char* keep, double* R,

@@ -27,9 +27,10 @@ __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
 // (longest-processing-time first): tiles differ several-fold in line count
 // (band clusters), and a one-shot grid of ~N/TPX workgroups leaves a long
 // tail of heavy tiles.
-template <int WPX>
+// CT: the plan uses the centre test (its LDS holds the zmax rows).
+template <int WPX, bool CT>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
-    __shared__ OpacityLds<WPX> sm;
+    __shared__ OpacityLds<WPX, CT> sm;
     __shared__ int s_it;
     load_pw_table(sm.pw, false);                       // visible after the first item fetch's barrier
     for (;;) {
@@ -38,18 +39,18 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
         const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= s.n_tiles) return;
-        dev_opacity_tile<WPX, false>(s, s.tile_order[it], chunk, sm);
+        dev_opacity_tile<WPX, false, CT>(s, s.tile_order[it], chunk, sm);
     }
 }
 
 // Adds the lines flagged wide_a (usually none) to the tiles they overlap.
-template <int WPX>
+template <int WPX, bool CT>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity_wide(StarDev s, int chunk) {
-    __shared__ OpacityLds<WPX> sm;
+    __shared__ OpacityLds<WPX, CT> sm;
     if (s.wide_any[0] == 0) return;                   // the usual case: no flagged line
     load_pw_table(sm.pw, false);
     __syncthreads();
-    for (int t = blockIdx.x; t < s.n_tiles; t += gridDim.x) dev_opacity_tile<WPX, true>(s, t, chunk, sm);
+    for (int t = blockIdx.x; t < s.n_tiles; t += gridDim.x) dev_opacity_tile<WPX, true, CT>(s, t, chunk, sm);
 }
 
 __global__ void k_reset_queue(int* ctr) { ctr[0] = 0; }
@@ -59,21 +60,36 @@ __global__ __launch_bounds__(256) void k_select(StarDev s, double eta, double bi
     dev_select(s, blockIdx.x * blockDim.x + threadIdx.x, eta, bin_ln, B, keep, R, Rd, n_keep);
 }
 
-int opacity_grid(int tile_px) {
+template <bool CT>
+static hipError_t opacity_occupancy(int tile_px, int* occ) {
+    switch (tile_px) {
+        case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<4, CT>, 512, 0);
+        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<8, CT>, 512, 0);
+        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<16, CT>, 512, 0);
+    }
+}
+
+int opacity_grid(int tile_px, bool center) {
     int dev = 0, n_cu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 1024;
-    hipError_t e = hipSuccess;
-    switch (tile_px) {
-        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_opacity<4>, 512, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_opacity<8>, 512, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_opacity<16>, 512, 0); break;
-    }
+    const hipError_t e = center ? opacity_occupancy<true>(tile_px, &occ) : opacity_occupancy<false>(tile_px, &occ);
     if (e != hipSuccess || occ < 1) occ = 1;
     return n_cu * occ;
 }
 
-__global__ __launch_bounds__(256) void k_flux(StarDev s) { dev_flux(s, blockIdx.x * blockDim.x + threadIdx.x); }
+// blockIdx.y = 0: the total branch, from an LDS copy of the pixel's
+// kappa_line column; blockIdx.y = 1: the continuum branch (reads no kappa_line).
+__global__ __launch_bounds__(64) void k_flux(StarDev s) {
+    __shared__ float kst[MAXD * WAVE];
+    const int i = blockIdx.x * WAVE + threadIdx.x;
+    if (blockIdx.y == 0) {
+        if (i < s.N) stage_kappa_column(s, i, kst + threadIdx.x);
+        dev_flux<true, false>(s, i, LdsKCol{kst + threadIdx.x});
+    } else {
+        dev_flux<false, true>(s, i, GlobalKCol{s.kappa + i, (size_t)s.Npad});
+    }
+}
 
 __global__ __launch_bounds__(64) void k_flux_e2(StarDev s) { dev_flux_e2(s, blockIdx.x * blockDim.x + threadIdx.x); }
 
@@ -81,8 +97,8 @@ __global__ __launch_bounds__(192) void k_flux_scatter(StarDev s) {
     dev_flux_scatter(s, blockIdx.x * 64 + threadIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(64) void k_reverse_scatter(StarDev s) {
-    dev_reverse_scatter(s, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(192) void k_reverse_scatter(StarDev s) {
+    dev_reverse_scatter(s, blockIdx.x * 64 + threadIdx.x);
 }
 
 __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, int quad, float* F) {
@@ -123,7 +139,10 @@ __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, i
 
 template <int MD>
 __global__ __launch_bounds__(64) void k_reverse_scan(StarDev s) {
-    dev_reverse_scan<MD>(s, blockIdx.x * blockDim.x + threadIdx.x);
+    __shared__ float kst[MD * WAVE];
+    const int i = blockIdx.x * WAVE + threadIdx.x;
+    if (i < s.N) stage_kappa_column(s, i, kst + threadIdx.x);
+    dev_reverse_scan<MD>(s, i, LdsKCol{kst + threadIdx.x});
 }
 
 template <int MD>
@@ -187,26 +206,31 @@ hipError_t launch_line_params(const StarDev& s, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
-    if (s.n_tiles == 0) return hipSuccess;
-    const int grid = std::max(1, std::min(s.grid_opacity, s.n_tiles));
-    k_reset_queue<<<1, 1, 0, st>>>(s.qctr);
+template <bool CT>
+static hipError_t launch_opacity_tiles(const StarDev& s, int chunk, int grid, hipStream_t st) {
     switch (s.tile_px) {
         case 32:
-            k_opacity<4><<<grid, 512, 0, st>>>(s, chunk);
-            k_opacity_wide<4><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity<4, CT><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity_wide<4, CT><<<grid, 512, 0, st>>>(s, chunk);
             break;
         case 64:
-            k_opacity<8><<<grid, 512, 0, st>>>(s, chunk);
-            k_opacity_wide<8><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity<8, CT><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity_wide<8, CT><<<grid, 512, 0, st>>>(s, chunk);
             break;
         case 128:
-            k_opacity<16><<<grid, 512, 0, st>>>(s, chunk);
-            k_opacity_wide<16><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity<16, CT><<<grid, 512, 0, st>>>(s, chunk);
+            k_opacity_wide<16, CT><<<grid, 512, 0, st>>>(s, chunk);
             break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_opacity(const StarDev& s, int chunk, hipStream_t st) {
+    if (s.n_tiles == 0) return hipSuccess;
+    const int grid = std::max(1, std::min(s.grid_opacity, s.n_tiles));
+    k_reset_queue<<<1, 1, 0, st>>>(s.qctr);
+    return s.center ? launch_opacity_tiles<true>(s, chunk, grid, st) : launch_opacity_tiles<false>(s, chunk, grid, st);
 }
 
 hipError_t launch_flux(const StarDev& s, hipStream_t st) {
@@ -215,13 +239,13 @@ hipError_t launch_flux(const StarDev& s, hipStream_t st) {
     else if (s.quad == PZ_QUAD_E2)
         k_flux_e2<<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else
-        k_flux<<<(s.N + 255) / 256, 256, 0, st>>>(s);
+        k_flux<<<dim3((s.N + WAVE - 1) / WAVE, 2), WAVE, 0, st>>>(s);
     return hipGetLastError();
 }
 
 hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st) {
     if (s.scatter)
-        k_reverse_scatter<<<(s.N + 63) / 64, 64, 0, st>>>(s);
+        k_reverse_scatter<<<(s.N + 63) / 64, dim3(64, 3), 0, st>>>(s);
     else if (s.quad == PZ_QUAD_E2)
         k_reverse_scan_e2<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else

@@ -19,40 +19,137 @@ __device__ __forceinline__ float detuning(int k, float delta, float h_hi, float 
 
 // -------------------------------------------------------------- opacity
 // A workgroup of 8 wavefronts owns TPX = 8 WPX consecutive pixels x all
-// depths.  The lines overlapping the tile are a contiguous range of the
-// sorted list; per chunk of lines, their per-depth parameters and the
-// detuning x of every (line, tile pixel) are staged in LDS (x = kNoLine
-// outside the line's window; real detunings satisfy |x| < 1e-2).
+// depths.  The lines overlapping the tile are a contiguous range [l0, l1) of
+// the sorted list, taken in chunks of at most MAX_CHUNK lines; chunk c holds
+// the lines l0 + c + q nch (q = 0, 1, ...; nch chunks), so every chunk spans
+// the tile's whole line range and the wavefronts' shares of a chunk are
+// alike (a chunk of neighbouring lines would leave the wavefronts beyond its
+// windows idle at the barrier).  Per chunk, the lines' per-depth parameters
+// and the detuning x of every (line, tile pixel) are staged in LDS (x =
+// kNoLine outside the line's window; real detunings satisfy |x| < 1e-2).
+// For the plain sum two LDS buffers alternate: the parameters of chunk c + 1
+// are copied from global memory straight into LDS while chunk c is summed,
+// and its detunings are written after, so each chunk costs one barrier.  A
+// workgroup that can meet the centre test stages one buffer and then sums it.
 //
 // Depths split as D = nfull NDG + r, NDG = 64/WPX.  Main part: wavefront w
 // covers pixels w WPX .. w WPX + WPX-1 of the tile, lane (px, dg) depths
 // j = d NDG + dg, d < nfull -- nearby detunings, so little divergence between
 // Voigt regions.  Tail: the TPX x r remaining (pixel, depth) pairs are dealt
-// to the first wavefronts 64 at a time (pixel t / r, depth nfull NDG + t % r),
-// so no lane idles on a partial depth group.  No atomics: every
-// (pixel, depth) sum is owned by one thread and runs in sorted-line order.
+// to the first wavefronts 64 at a time (pixel t / r, depth nfull NDG + t % r).
+// No atomics: every (pixel, depth) sum is owned by one thread and runs in a
+// fixed line order (chunk by chunk).
 static constexpr int MAX_CHUNK = 16;
 static constexpr float kNoLine = 2.0f;
 
-// The opacity loop is VALU-issue bound, so resident wavefronts matter more
-// than the few spills a register cap costs (they fall in the per-tile and
-// per-chunk code, not the evaluation loop): 8 waves per SIMD for 4-pixel
-// wavefronts, 6 for the wider ones.
-#define PZ_OPACITY_WAVES(WPX) __attribute__((amdgpu_waves_per_eu((WPX) == 4 ? 8 : 6)))
+// Resident wavefronts per SIMD.  Six for 4-pixel wavefronts: the 80 VGPRs
+// keep the straight-line wing sums of all depth groups in registers, and
+// three workgroups per CU still overlap one another's barriers.
+#define PZ_OPACITY_WAVES(WPX) __attribute__((amdgpu_waves_per_eu(6)))
 
-template <int WPX>
+// LDS of one workgroup: chunk buffers of parameter rows (rows of D) and
+// detunings -- two, alternating, for the plain sum; one with the centre
+// test (CT), whose zmax rows take the room of the second and which so keeps
+// three workgroups per CU -- and the piecewise core table.
+template <int WPX, bool CT>
 struct OpacityLds {
-    float4 lp[MAX_CHUNK * MAXD];
-    float zmax[MAX_CHUNK * MAXD];                     // centre test only
-    float x[MAX_CHUNK * 8 * WPX];
-    float4 pw[PZ_PW_N * 4];                           // piecewise core table
+    static constexpr int NB = CT ? 1 : 2;
+    float4 lp[NB][MAX_CHUNK * MAXD];
+    float x[NB][MAX_CHUNK * 8 * WPX];
+    float zmax[CT ? MAX_CHUNK * MAXD : 1];
+    float4 pw[PZ_PW_N * 4];
 };
+
+// Copies of chunk c's parameter rows (and, CT, zmax rows) into buffer b:
+// LDS element k = q D + j of the chunk is row l0 + c + q nch, depth j.  Each
+// wavefront instruction moves 64 elements from global memory straight into
+// consecutive LDS slots; they are complete once the issuing wavefront's load
+// counter drains.
+template <int WPX, bool CT, class Lds>
+__device__ __forceinline__ void stage_rows(const StarDev& s, int l0, int c, int nch, int nc, int b, Lds& sm) {
+    constexpr int LPT = (MAX_CHUNK * MAXD + 511) / 512;
+    const int D = s.D, n = nc * D;
+    const int lane = threadIdx.x % WAVE;
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+        const int k0 = u * 512 + (threadIdx.x & ~(WAVE - 1));   // wavefront-uniform
+        const int k = k0 + lane;
+        if (k0 < n && k < n) {
+            const int q = k / D;
+            const size_t g = (size_t)(l0 + c + q * nch) * D + (k - q * D);
+            __builtin_amdgcn_global_load_lds((const void*)(s.lp + g),
+                                             (__attribute__((address_space(3))) void*)(&sm.lp[b][k0]), 16, 0, 0);
+            if (CT)
+                __builtin_amdgcn_global_load_lds((const void*)(s.zmax + g),
+                                                 (__attribute__((address_space(3))) void*)(&sm.zmax[k0]), 4, 0, 0);
+        }
+    }
+}
+
+// The window fields of a thread's staged (line, pixel) pairs, loaded before
+// a chunk is summed and turned into detunings after.
+template <int WPX>
+struct XFields {
+    static constexpr int XPT = (MAX_CHUNK * 8 * WPX + 511) / 512;
+    int lo[XPT], hi[XPT], ic[XPT];
+    float dl[XPT];
+};
+
+template <int WPX, bool WIDE>
+__device__ __forceinline__ void load_xfields(const StarDev& s, int l0, int c, int nch, int nc, bool any_wide,
+                                             XFields<WPX>& f) {
+    constexpr int TPX = 8 * WPX;
+#pragma unroll
+    for (int u = 0; u < XFields<WPX>::XPT; ++u) {
+        const int k = threadIdx.x + u * 512;
+        const int l = l0 + c + min(k / TPX, nc - 1) * nch;
+        f.lo[u] = s.ln.ilo[l];
+        f.hi[u] = s.ln.ihi[l];
+        f.ic[u] = s.ln.ic[l];
+        f.dl[u] = s.ln.delta[l];
+        // a line the pass does not take gets an empty window
+        if ((any_wide && s.wide_a[l] != 0) != WIDE) f.hi[u] = f.lo[u] - 1;
+    }
+}
+
+template <int WPX, bool CT, class Lds>
+__device__ __forceinline__ void write_x(const StarDev& s, int l0, int c, int nch, int nc, int p0, int b,
+                                        const XFields<WPX>& f, Lds& sm) {
+    constexpr int TPX = 8 * WPX;
+#pragma unroll
+    for (int u = 0; u < XFields<WPX>::XPT; ++u) {
+        const int k = threadIdx.x + u * 512;
+        if (k < nc * TPX) {
+            const int q = k / TPX, i = p0 + (k - q * TPX);
+            float x = kNoLine;
+            if (i >= f.lo[u] && i <= f.hi[u]) x = detuning(i - f.ic[u], f.dl[u], s.h_hi, s.h_lo);
+            // the slack keeps every lane the per-depth test would accept
+            if (CT && !(fabsf(x) <= s.xlim[l0 + c + q * nch] * (1.0f + 1e-5f))) x = kNoLine;
+            sm.x[b][k] = x;
+        }
+    }
+}
+
+// The wing sums of one line over a lane's depth groups d < nfull, all with
+// the NP-pair quadrature; CT keeps only the pairs with z2 <= zmax.
+template <int NP, bool CT, int DPT, int NDG>
+__device__ __forceinline__ void wing_sums(float* acc, const float4* pd, const float* z2, const float* zrow, int dg,
+                                          int nfull, const float* T2, const float* W) {
+#pragma unroll
+    for (int d = 0; d < DPT; ++d)
+        if (d < nfull) {
+            const bool keep = !CT || z2[d] <= zrow[d * NDG + dg];
+            if (CT && !__any(keep)) continue;          // the whole wavefront drops this group
+            const float a = fmaf(pd[d].w, wing_S<NP>(pd[d].y, z2[d], T2, W), acc[d]);
+            acc[d] = keep ? a : acc[d];
+        }
+}
 
 // With the centre test (CT) a pixel's detuning is marked kNoLine beyond the
 // line's largest span, and a (pixel, depth) lane evaluates only where
 // v^2 + a^2 <= zmax of its (line, depth).
-template <int WPX, bool CT, bool WIDE>
-__device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
+template <int WPX, bool CT, bool WIDE, class Lds>
+__device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, Lds& sm) {
     constexpr int NDG = 64 / WPX;
     constexpr int DPT = MAXD / NDG;                    // most full depth groups
     constexpr int TPX = 8 * WPX;
@@ -80,47 +177,82 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 #pragma unroll
     for (int d = 0; d < DPT; ++d) acc[d] = 0.0f;
 
-    for (int c0 = l0; c0 < l1; c0 += chunk) {
-        const int nc = min(chunk, l1 - c0);
-        const float4* src = s.lp + (size_t)c0 * D;
-        for (int k = tid; k < nc * D; k += 512) {
-            const int q = k / D;
-            sm.lp[q * MAXD + (k - q * D)] = src[k];
-            if (CT) sm.zmax[q * MAXD + (k - q * D)] = s.zmax[(size_t)c0 * D + k];
+    const int nl = l1 - l0;
+    const int nch = (nl + chunk - 1) / chunk;
+    auto lines_in = [&](int c) { return (nl - c + nch - 1) / nch; };
+    constexpr bool DB = Lds::NB == 2;                  // double-buffered chunks
+    static_assert(!CT || !DB, "the centre test stages one buffer");
+    XFields<WPX> f;
+    if (DB) {
+        if (nch > 0) {
+            stage_rows<WPX, CT>(s, l0, 0, nch, lines_in(0), 0, sm);
+            load_xfields<WPX, WIDE>(s, l0, 0, nch, lines_in(0), any_wide, f);
+            write_x<WPX, CT>(s, l0, 0, nch, lines_in(0), p0, 0, f, sm);
         }
-        for (int k = tid; k < nc * TPX; k += 512) {
-            const int q = k / TPX, i = p0 + (k - q * TPX);
-            const int l = c0 + q;
-            float x = kNoLine;
-            if (i >= s.ln.ilo[l] && i <= s.ln.ihi[l] && (any_wide && s.wide_a[l] != 0) == WIDE)
-                x = detuning(i - s.ln.ic[l], s.ln.delta[l], s.h_hi, s.h_lo);
-            // the slack keeps every lane the per-depth test would accept
-            if (CT && !(fabsf(x) <= s.xlim[l] * (1.0f + 1e-5f))) x = kNoLine;
-            sm.x[k] = x;
-        }
+        __builtin_amdgcn_s_waitcnt(0);                // the LDS copies count as loads
         __syncthreads();
+    }
+    for (int c = 0; c < nch; ++c) {
+        const int b = DB ? (c & 1) : 0, nc = lines_in(c);
+        const bool more = DB && c + 1 < nch;
+        if (!DB) {                                     // one buffer: stage, then sum
+            stage_rows<WPX, CT>(s, l0, c, nch, nc, 0, sm);
+            load_xfields<WPX, WIDE>(s, l0, c, nch, nc, any_wide, f);
+            write_x<WPX, CT>(s, l0, c, nch, nc, p0, 0, f, sm);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        } else if (more) {                             // chunk c + 1 into the other buffer
+            stage_rows<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), b ^ 1, sm);
+            load_xfields<WPX, WIDE>(s, l0, c + 1, nch, lines_in(c + 1), any_wide, f);
+        }
+        const float4* rows = sm.lp[b];
         for (int q = 0; q < nc; ++q) {
-            const float4* row = sm.lp + q * MAXD;
-            const float* zrow = sm.zmax + q * MAXD;
-            const float x = sm.x[q * TPX + px];
+            const float4* row = rows + q * D;
+            const float* zrow = CT ? &sm.zmax[q * D] : nullptr;
+            const float x = sm.x[b][q * TPX + px];
             if (x < 1.0f) {
+                float4 pd[DPT];
+                float z2[DPT];
+                float zmin = 3.0e38f;
 #pragma unroll
                 for (int d = 0; d < DPT; ++d) {
-                    if (d < nfull) {
-                        const float4 p = row[d * NDG + dg];
-                        acc[d] = voigt_acc<CT, WIDE>(acc[d], p.y, p.z, p.w, x * p.x, sm.pw,
-                                                     CT ? zrow[d * NDG + dg] : 0.0f);
+                    pd[d] = row[d * NDG + dg];         // rows of D: the read past D of the last
+                    const float v = x * pd[d].x;       // groups stays inside the buffer, unused
+                    z2[d] = fmaf(v, v, pd[d].y);
+                    if (d < nfull) zmin = fminf(zmin, z2[d]);
+                }
+                if (!WIDE && __all(zmin >= PZ_VOIGT_WING_R2)) {
+                    // Every lane of every depth group is in the wing: one
+                    // wavefront-uniform tier (the most accurate any of them
+                    // needs) and straight-line sums.  A line not flagged
+                    // wide_a keeps each tier's pair products in range.
+                    if (__all(zmin >= PZ_VOIGT_TIER3_R2))
+                        wing_sums<1, CT, DPT, NDG>(acc, pd, z2, zrow, dg, nfull, PZ_GH2_T2, PZ_GH2_W);
+                    else if (__all(zmin >= PZ_VOIGT_TIER2_R2))
+                        wing_sums<2, CT, DPT, NDG>(acc, pd, z2, zrow, dg, nfull, PZ_GH4_T2, PZ_GH4_W);
+                    else
+                        wing_sums<3, CT, DPT, NDG>(acc, pd, z2, zrow, dg, nfull, PZ_GH6_T2, PZ_GH6_W);
+                } else {
+#pragma unroll
+                    for (int d = 0; d < DPT; ++d) {
+                        if (d < nfull) {
+                            const float4 p = pd[d];
+                            acc[d] = voigt_acc<CT, WIDE>(acc[d], p.y, p.z, p.w, x * p.x, sm.pw,
+                                                         CT ? zrow[d * NDG + dg] : 0.0f);
+                        }
                     }
                 }
             }
             if (tail) {
-                const float xt = sm.x[q * TPX + tpx];
+                const float xt = sm.x[b][q * TPX + tpx];
                 if (xt < 1.0f) {
                     const float4 p = row[tj];
                     acc_t = voigt_acc<CT, WIDE>(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw, CT ? zrow[tj] : 0.0f);
                 }
             }
         }
+        if (more) write_x<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), p0, b ^ 1, f, sm);
+        if (DB) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
     const int i = p0 + px;
@@ -143,11 +275,12 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 // writes the tile's opacity from every line not flagged wide_a; the wide
 // pass then adds the flagged lines (whose damping ratio spans both near and
 // far wing tiers across depths) with the evaluator that keeps each lane on
-// its own tier, so the main pass's code stays as lean as before.
-template <int WPX, bool WIDE>
-__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX>& sm) {
-    if (s.center)
-        opacity_tile_body<WPX, true, WIDE>(s, tile, chunk, sm);
+// its own tier.  ANYCT: the workgroup's LDS has the centre test's rows, so
+// stars with the centre test are taken too.
+template <int WPX, bool WIDE, bool ANYCT>
+__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX, ANYCT>& sm) {
+    if (ANYCT && s.center)
+        opacity_tile_body<WPX, ANYCT, WIDE>(s, tile, chunk, sm);
     else
         opacity_tile_body<WPX, false, WIDE>(s, tile, chunk, sm);
 }

@@ -23,6 +23,9 @@
 //   dL/dtau  += VJP of J(S*, tau) with the cotangent (1 - eps) lambda,
 //   dL/dchi   = trapezoid adjoint of dL/dtau,
 //   dL/dkappa_line_j = dL/dchi_j + dL/deps_j sigma_j / chi_j^2.
+// It runs on the same three threads per pixel (one per ray direction), reuses
+// the forward's segment tables, so no exponential is evaluated, and adds the
+// directions' partial sums in a fixed order.
 // Workspace columns are [D] with stride Npad (coalesced across pixels).
 #pragma once
 
@@ -34,12 +37,13 @@ struct Col {
     __device__ __forceinline__ double& operator[](int j) const { return p[(size_t)j * st]; }
 };
 
-// workspace arrays (each [D][Npad] float64): per branch b (tau, eps, S, J, Ld, B and the three
-// per-direction parts of J), then the backward ones
-// and the segment coefficients of each direction m (e^-x, 1 - e^-x, lw(x) of the segment ending at
-// depth j, j >= 1, and of the surface segment [0, tau_0] at j = 0)
-enum { SC_BR = 0, SC_TAU = 0, SC_EPS = 1, SC_S = 2, SC_J = 3, SC_LD = 4, SC_B = 5, SC_JM = 6, SC_CE = 9,
-       SC_CO = 12, SC_CL = 15, SC_PER_BR = 18, SC_LAM = 36, SC_RHS = 37, SC_GT = 38, SC_IS = 39, SC_NARR = 42 };
+// workspace arrays (each [D][Npad] float64): per branch b (tau, eps, S, Ld, B, the three
+// per-direction parts of J and the segment coefficients of each direction m: e^-x, 1 - e^-x, lw(x)
+// of the segment ending at depth j, j >= 1, and of the surface segment [0, tau_0] at j = 0), then
+// the backward's lambda, right-hand side and one intensity profile per direction.  The backward
+// keeps its per-direction partial sums in the continuum branch's columns, which it does not need.
+enum { SC_BR = 0, SC_TAU = 0, SC_EPS = 1, SC_S = 2, SC_LD = 3, SC_B = 4, SC_JM = 5, SC_CE = 8, SC_CO = 11,
+       SC_CL = 14, SC_PER_BR = 17, SC_LAM = 34, SC_RHS = 35, SC_IS = 36, SC_NARR = 39 };
 static_assert(SC_NARR == SC_WS_ARRAYS, "scattering workspace size");
 
 __device__ __forceinline__ Col sc_col(const StarDev& s, int id, int i) {
@@ -51,306 +55,11 @@ __device__ __forceinline__ Col sc_bcol(const StarDev& s, int b, int k, int i) {
 __device__ __forceinline__ double sc_mu(int k) { return k == 0 ? kMu0 : (k == 1 ? kMu1 : kMu2); }
 __device__ __forceinline__ double sc_hw(int k) { return k == 1 ? 0.5 * 8.0 / 18.0 : 0.5 * 5.0 / 18.0; }   // w_k / 2
 
-// J = Lambda S
-__device__ inline void sc_lambda(int D, const Col& tau, const Col& S, const Col& J) {
-    double I[3];
-    {   // inward, from the surface
-        const double t0 = tau[0], S0 = S[0];
-        const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
-            I[k] = S0 * et.om + (S_top - S0) * et.lw;
-            acc += sc_hw(k) * I[k];
-        }
-        J[0] = acc;
-    }
-    double ta = tau[0], Sa = S[0];
-    for (int j = 1; j < D; ++j) {
-        const double tb = tau[j], Sb = S[j];
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms64 et = exp_terms64((tb - ta) / sc_mu(k));
-            I[k] = I[k] * et.e + Sb * et.om + (Sa - Sb) * et.lw;
-            acc += sc_hw(k) * I[k];
-        }
-        J[j] = acc;
-        ta = tb;
-        Sa = Sb;
-    }
-    {   // outward, from the diffusion boundary
-        const double SD = S[D - 1];
-        const double grad = (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            I[k] = SD + sc_mu(k) * grad;
-            acc += sc_hw(k) * I[k];
-        }
-        J[D - 1] += acc;
-    }
-    double tb = tau[D - 1], Sb = S[D - 1];
-    for (int j = D - 2; j >= 0; --j) {
-        const double t = tau[j], Sj = S[j];
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms64 et = exp_terms64((tb - t) / sc_mu(k));
-            I[k] = I[k] * et.e + Sj * et.om + (Sb - Sj) * et.lw;
-            acc += sc_hw(k) * I[k];
-        }
-        J[j] += acc;
-        tb = t;
-        Sb = Sj;
-    }
-}
-
-// out = Lambda^T v
-__device__ inline void sc_lambda_T(int D, const Col& tau, const Col& v, const Col& out) {
-    for (int j = 0; j < D; ++j) out[j] = 0.0;
-    double G[3] = {0.0, 0.0, 0.0};
-    // reverse of the inward sweep (deepest first)
-    for (int j = D - 1; j >= 1; --j) {
-        const double vj = v[j], x0 = tau[j] - tau[j - 1];
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            G[k] += sc_hw(k) * vj;
-            const ExpTerms64 et = exp_terms64(x0 / sc_mu(k));
-            a += G[k] * (et.om - et.lw);
-            b += G[k] * et.lw;
-            G[k] *= et.e;
-        }
-        out[j] += a;
-        out[j - 1] += b;
-    }
-    {
-        const double t0 = tau[0], c = t0 / (tau[1] - t0), v0 = v[0];
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            G[k] += sc_hw(k) * v0;
-            const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
-            a += G[k] * (et.om + c * et.lw);
-            b -= G[k] * c * et.lw;
-        }
-        out[0] += a;
-        out[1] += b;
-    }
-    // reverse of the outward sweep (surface first)
-    G[0] = G[1] = G[2] = 0.0;
-    for (int j = 0; j < D - 1; ++j) {
-        const double vj = v[j], x0 = tau[j + 1] - tau[j];
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            G[k] += sc_hw(k) * vj;
-            const ExpTerms64 et = exp_terms64(x0 / sc_mu(k));
-            a += G[k] * (et.om - et.lw);
-            b += G[k] * et.lw;
-            G[k] *= et.e;
-        }
-        out[j] += a;
-        out[j + 1] += b;
-    }
-    {
-        const double g = 1.0 / (tau[D - 1] - tau[D - 2]), vD = v[D - 1];
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            G[k] += sc_hw(k) * vD;
-            a += G[k] * (1.0 + sc_mu(k) * g);
-            b -= G[k] * sc_mu(k) * g;
-        }
-        out[D - 1] += a;
-        out[D - 2] += b;
-    }
-}
-
-// Outward intensities I+_j(mu_k) into IS[k] (bottom-up)
-__device__ inline void sc_store_out(int D, const Col& tau, const Col& S, const Col* IS) {
-    const double SD = S[D - 1];
-    const double grad = (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
-    double I[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        I[k] = SD + sc_mu(k) * grad;
-        IS[k][D - 1] = I[k];
-    }
-    double tb = tau[D - 1], Sb = SD;
-    for (int j = D - 2; j >= 0; --j) {
-        const double t = tau[j], Sj = S[j];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms64 et = exp_terms64((tb - t) / sc_mu(k));
-            I[k] = I[k] * et.e + Sj * et.om + (Sb - Sj) * et.lw;
-            IS[k][j] = I[k];
-        }
-        tb = t;
-        Sb = Sj;
-    }
-}
-
-// Inward intensities I-_j(mu_k) into IS[k] (top-down)
-__device__ inline void sc_store_in(int D, const Col& tau, const Col& S, const Col* IS) {
-    const double t0 = tau[0], S0 = S[0];
-    const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
-    double I[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const ExpTerms64 et = exp_terms64(t0 / sc_mu(k));
-        I[k] = S0 * et.om + (S_top - S0) * et.lw;
-        IS[k][0] = I[k];
-    }
-    double ta = t0, Sa = S0;
-    for (int j = 1; j < D; ++j) {
-        const double tb = tau[j], Sb = S[j];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const ExpTerms64 et = exp_terms64((tb - ta) / sc_mu(k));
-            I[k] = I[k] * et.e + Sb * et.om + (Sa - Sb) * et.lw;
-            IS[k][j] = I[k];
-        }
-        ta = tb;
-        Sa = Sb;
-    }
-}
-
 // d(S_top)/d(tau_0), d(S_top)/d(tau_1) with S_top = S_0 - tau_0 (S_1 - S_0) / (tau_1 - tau_0)
 __device__ __forceinline__ void sc_top_dtau(const Col& tau, const Col& S, double& d0, double& d1) {
     const double t0 = tau[0], dt = tau[1] - t0, sig = (S[1] - S[0]) / dt;
     d0 = -sig - t0 * sig / dt;
     d1 = t0 * sig / dt;
-}
-
-// Flux VJP for the seed G: writes dF/dS G into gS and adds the tau terms to gt.
-__device__ inline void sc_flux_vjp(int D, const Col& tau, const Col& S, double G, const Col& gS, const Col& gt,
-                                   const Col* IS) {
-    sc_store_out(D, tau, S, IS);
-    for (int j = 0; j < D; ++j) gS[j] = 0.0;
-    const double t0 = tau[0], S0 = S[0], dt01 = tau[1] - t0;
-    const double S_top = S0 - t0 * (S[1] - S0) / dt01;
-    double d0, d1;
-    sc_top_dtau(tau, S, d0, d1);
-    double Gk[3];
-    double gStop = 0.0, gS0 = 0.0, gt0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double mu = sc_mu(k);
-        const double g0 = G * 2.0 * PI * 2.0 * sc_hw(k) * mu;      // dL/dI(0, mu_k)
-        const ExpTerms64 et = exp_terms64(t0 / mu);
-        const double Iin = IS[k][0];                                  // I+ at tau_0
-        gt0 += g0 * (-Iin * et.e + S_top * et.e + (S0 - S_top) * et.dlw) / mu;
-        gStop += g0 * (et.om - et.lw);
-        gS0 += g0 * et.lw;
-        Gk[k] = g0 * et.e;                                            // dL/dI+(tau_0)
-    }
-    gS[0] += gS0 + gStop * (1.0 + t0 / dt01);
-    gS[1] += gStop * (-t0 / dt01);
-    gt[0] += gt0 + gStop * d0;
-    gt[1] += gStop * d1;
-    for (int j = 0; j < D - 1; ++j) {
-        const double t = tau[j], tn = tau[j + 1], Sj = S[j], Sn = S[j + 1];
-        double a = 0.0, b = 0.0, gx = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double mu = sc_mu(k);
-            const ExpTerms64 et = exp_terms64((tn - t) / mu);
-            gx += Gk[k] * (-IS[k][j + 1] * et.e + Sj * et.e + (Sn - Sj) * et.dlw) / mu;
-            a += Gk[k] * (et.om - et.lw);
-            b += Gk[k] * et.lw;
-            Gk[k] *= et.e;
-        }
-        gS[j] += a;
-        gS[j + 1] += b;
-        gt[j + 1] += gx;
-        gt[j] -= gx;
-    }
-    {
-        const double dS = S[D - 1] - S[D - 2], dt = tau[D - 1] - tau[D - 2];
-        double a = 0.0, b = 0.0, gd = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double mu = sc_mu(k);
-            a += Gk[k] * (1.0 + mu / dt);
-            b -= Gk[k] * mu / dt;
-            gd += Gk[k] * (-mu * dS / (dt * dt));
-        }
-        gS[D - 1] += a;
-        gS[D - 2] += b;
-        gt[D - 1] += gd;
-        gt[D - 2] -= gd;
-    }
-}
-
-// Adds to gt the tau part of the VJP of J(S, tau) for the cotangent u.
-__device__ inline void sc_lambda_tau_vjp(int D, const Col& tau, const Col& S, const Col& u, const Col& gt,
-                                         const Col* IS) {
-    double G[3];
-    // inward: forward profiles, then the reverse sweep from the deepest layer
-    sc_store_in(D, tau, S, IS);
-    G[0] = G[1] = G[2] = 0.0;
-    for (int j = D - 1; j >= 1; --j) {
-        const double uj = u[j], t = tau[j], tp = tau[j - 1], Sj = S[j], Sp = S[j - 1];
-        double gx = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double mu = sc_mu(k);
-            G[k] += sc_hw(k) * uj;
-            const ExpTerms64 et = exp_terms64((t - tp) / mu);
-            gx += G[k] * (-IS[k][j - 1] * et.e + Sj * et.e + (Sp - Sj) * et.dlw) / mu;
-            G[k] *= et.e;
-        }
-        gt[j] += gx;
-        gt[j - 1] -= gx;
-    }
-    {
-        const double t0 = tau[0], S0 = S[0];
-        const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
-        double d0, d1;
-        sc_top_dtau(tau, S, d0, d1);
-        double gx = 0.0, gStop = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double mu = sc_mu(k);
-            G[k] += sc_hw(k) * u[0];
-            const ExpTerms64 et = exp_terms64(t0 / mu);
-            gx += G[k] * (S0 * et.e + (S_top - S0) * et.dlw) / mu;
-            gStop += G[k] * et.lw;
-        }
-        gt[0] += gx + gStop * d0;
-        gt[1] += gStop * d1;
-    }
-    // outward: forward profiles, then the reverse sweep from the surface
-    sc_store_out(D, tau, S, IS);
-    G[0] = G[1] = G[2] = 0.0;
-    for (int j = 0; j < D - 1; ++j) {
-        const double uj = u[j], t = tau[j], tn = tau[j + 1], Sj = S[j], Sn = S[j + 1];
-        double gx = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double mu = sc_mu(k);
-            G[k] += sc_hw(k) * uj;
-            const ExpTerms64 et = exp_terms64((tn - t) / mu);
-            gx += G[k] * (-IS[k][j + 1] * et.e + Sj * et.e + (Sn - Sj) * et.dlw) / mu;
-            G[k] *= et.e;
-        }
-        gt[j + 1] += gx;
-        gt[j] -= gx;
-    }
-    {
-        const double dS = S[D - 1] - S[D - 2], dt = tau[D - 1] - tau[D - 2];
-        double gd = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            G[k] += sc_hw(k) * u[D - 1];
-            gd += G[k] * (-sc_mu(k) * dS / (dt * dt));
-        }
-        gt[D - 1] += gd;
-        gt[D - 2] -= gd;
-    }
 }
 
 struct ScPixel {
@@ -539,52 +248,255 @@ __device__ inline void dev_flux_scatter(const StarDev& s, int i, int b) {
     }
 }
 
-// Backward of the total branch: writes dL/dkappa_line into gk.
-__device__ inline void dev_reverse_scatter(const StarDev& s, int i) {
-    if (i >= s.N) return;
-    const int D = s.D;
-    const ScPixel p = sc_pixel(s, i);
-    const Col B = sc_bcol(s, 0, SC_B, i), tau = sc_bcol(s, 0, SC_TAU, i), eps = sc_bcol(s, 0, SC_EPS, i),
-              S = sc_bcol(s, 0, SC_S, i), J = sc_bcol(s, 0, SC_J, i), Ld = sc_bcol(s, 0, SC_LD, i);
-    const Col lam = sc_col(s, SC_LAM, i), rhs = sc_col(s, SC_RHS, i), gt = sc_col(s, SC_GT, i);
-    const Col U = sc_bcol(s, 1, SC_S, i), T = sc_bcol(s, 1, SC_J, i);   // continuum-branch columns as scratch
-    const Col IS[3] = {sc_col(s, SC_IS, i), sc_col(s, SC_IS + 1, i), sc_col(s, SC_IS + 2, i)};
-    for (int j = 0; j < D; ++j) gt[j] = 0.0;
-    sc_flux_vjp(D, tau, S, (double)s.dLdF[i], rhs, gt, IS);
-    // adjoint fixed point: lambda = rhs + Lambda^T ((1 - eps) lambda)
-    for (int j = 0; j < D; ++j) lam[j] = rhs[j];
-    int it = 0;
-    while (it < s.sc_max_iter) {
-        ++it;
-        for (int j = 0; j < D; ++j) U[j] = (1.0 - eps[j]) * lam[j];
-        sc_lambda_T(D, tau, U, T);
-        double dmax = 0.0, lmax = 0.0;
-        for (int j = 0; j < D; ++j) {
-            const double e = eps[j], lj = lam[j];
-            const double ln = lj + (rhs[j] + T[j] - lj) / (1.0 - (1.0 - e) * Ld[j]);
-            dmax = fmax(dmax, fabs(ln - lj));
-            lmax = fmax(lmax, fabs(ln));
-            lam[j] = ln;
-        }
-        if (dmax <= s.sc_tol * lmax) break;
+// lw'(x) = e^-x - lw(x) / x of a segment of length x with coefficients e^-x and lw(x)
+__device__ __forceinline__ double sc_dlw(double e, double lw, double x) { return e - lw / x; }
+
+// I+_j along direction m into IS (bottom-up), from the segment tables
+__device__ inline void sc_out_mu(int D, const Col& tau, const Col& S, int m, const Col& CE, const Col& CO,
+                                 const Col& CL, const Col& IS) {
+    const double SD = S[D - 1];
+    double I = SD + sc_mu(m) * (SD - S[D - 2]) / (tau[D - 1] - tau[D - 2]);
+    IS[D - 1] = I;
+    double Sb = SD;
+    for (int j = D - 2; j >= 0; --j) {
+        const double Sj = S[j];
+        I = I * CE[j + 1] + Sj * CO[j + 1] + (Sb - Sj) * CL[j + 1];
+        IS[j] = I;
+        Sb = Sj;
     }
-    if (s.sc_iters) s.sc_iters[2 * s.Npad + i] = it;
-    // J* and the eps and tau terms of the fixed point
-    sc_lambda(D, tau, S, J);
-    for (int j = 0; j < D; ++j) U[j] = (1.0 - eps[j]) * lam[j];
-    sc_lambda_tau_vjp(D, tau, S, U, gt, IS);
+}
+
+// I-_j along direction m into IS (top-down)
+__device__ inline void sc_in_mu(int D, const Col& tau, const Col& S, const Col& CE, const Col& CO, const Col& CL,
+                                const Col& IS) {
+    const double t0 = tau[0], S0 = S[0];
+    const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+    double I = S0 * CO[0] + (S_top - S0) * CL[0];
+    IS[0] = I;
+    double Sa = S0;
+    for (int j = 1; j < D; ++j) {
+        const double Sb = S[j];
+        I = I * CE[j] + Sb * CO[j] + (Sa - Sb) * CL[j];
+        IS[j] = I;
+        Sa = Sb;
+    }
+}
+
+// Direction m's part of the flux VJP for the seed G = dL/dF: its dF/dS G into gS and its tau
+// terms into gt (both overwritten); leaves I+ of S in IS.
+__device__ inline void sc_flux_vjp_mu(int D, const Col& tau, const Col& S, double G, int m, const Col& CE,
+                                      const Col& CO, const Col& CL, const Col& IS, const Col& gS, const Col& gt) {
+    sc_out_mu(D, tau, S, m, CE, CO, CL, IS);
+    for (int j = 2; j < D; ++j) {
+        gS[j] = 0.0;
+        gt[j] = 0.0;
+    }
+    const double mu = sc_mu(m);
+    const double t0 = tau[0], S0 = S[0], dt01 = tau[1] - t0;
+    const double S_top = S0 - t0 * (S[1] - S0) / dt01;
+    double d0, d1;
+    sc_top_dtau(tau, S, d0, d1);
+    const double g0 = G * 2.0 * PI * 2.0 * sc_hw(m) * mu;           // dL/dI(0, mu_m)
+    {
+        const double e = CE[0], lw = CL[0], dlw = sc_dlw(e, lw, t0 / mu);
+        const double gStop = g0 * (CO[0] - lw);
+        gt[0] = g0 * (-IS[0] * e + S_top * e + (S0 - S_top) * dlw) / mu + gStop * d0;
+        gt[1] = gStop * d1;
+        gS[0] = g0 * lw + gStop * (1.0 + t0 / dt01);
+        gS[1] = gStop * (-t0 / dt01);
+    }
+    double Gk = g0 * CE[0];                                           // dL/dI+(tau_0)
+    for (int j = 0; j < D - 1; ++j) {
+        const double Sj = S[j], Sn = S[j + 1];
+        const double e = CE[j + 1], lw = CL[j + 1], dlw = sc_dlw(e, lw, (tau[j + 1] - tau[j]) / mu);
+        const double gx = Gk * (-IS[j + 1] * e + Sj * e + (Sn - Sj) * dlw) / mu;
+        gS[j] += Gk * (CO[j + 1] - lw);
+        gS[j + 1] += Gk * lw;
+        gt[j + 1] += gx;
+        gt[j] -= gx;
+        Gk *= e;
+    }
+    {
+        const double dS = S[D - 1] - S[D - 2], dt = tau[D - 1] - tau[D - 2];
+        gS[D - 1] += Gk * (1.0 + mu / dt);
+        gS[D - 2] -= Gk * mu / dt;
+        const double gd = Gk * (-mu * dS / (dt * dt));
+        gt[D - 1] += gd;
+        gt[D - 2] -= gd;
+    }
+}
+
+// out = direction m's part of Lambda^T v (overwritten).  Each sweep carries the pending term of
+// the next depth, so the first sweep writes every element once and the second adds once.
+__device__ inline void sc_lambda_T_mu(int D, const Col& tau, const Col& v, const Col& out, int m, const Col& CE,
+                                      const Col& CO, const Col& CL) {
+    const double mu = sc_mu(m), hw = sc_hw(m);
+    // transpose of the outward sweep, surface first
+    double G = 0.0, carry = 0.0;
+    for (int j = 0; j < D - 1; ++j) {
+        G += hw * v[j];
+        const double lw = CL[j + 1];
+        out[j] = carry + G * (CO[j + 1] - lw);
+        carry = G * lw;
+        G *= CE[j + 1];
+    }
+    {
+        const double g = mu / (tau[D - 1] - tau[D - 2]);
+        G += hw * v[D - 1];
+        out[D - 1] = carry + G * (1.0 + g);
+        out[D - 2] -= G * g;
+    }
+    // transpose of the inward sweep, deepest first
+    G = 0.0;
+    carry = 0.0;
+    for (int j = D - 1; j >= 1; --j) {
+        G += hw * v[j];
+        const double lw = CL[j];
+        out[j] += carry + G * (CO[j] - lw);
+        carry = G * lw;
+        G *= CE[j];
+    }
+    {
+        const double t0 = tau[0], c = t0 / (tau[1] - t0);
+        G += hw * v[0];
+        out[0] += carry + G * (CO[0] + c * CL[0]);
+        out[1] -= G * c * CL[0];
+    }
+}
+
+// Adds to gt direction m's tau terms of the VJP of J(S, tau) for the cotangent u.  IS holds I+ of
+// S on entry and I- of S on exit.
+__device__ inline void sc_lambda_tau_vjp_mu(int D, const Col& tau, const Col& S, const Col& u, int m, const Col& CE,
+                                            const Col& CO, const Col& CL, const Col& IS, const Col& gt) {
+    const double mu = sc_mu(m), hw = sc_hw(m);
+    // outward: reverse sweep from the surface over the stored I+
+    double G = 0.0;
+    for (int j = 0; j < D - 1; ++j) {
+        const double Sj = S[j], Sn = S[j + 1];
+        G += hw * u[j];
+        const double e = CE[j + 1], dlw = sc_dlw(e, CL[j + 1], (tau[j + 1] - tau[j]) / mu);
+        const double gx = G * (-IS[j + 1] * e + Sj * e + (Sn - Sj) * dlw) / mu;
+        G *= e;
+        gt[j + 1] += gx;
+        gt[j] -= gx;
+    }
+    {
+        const double dS = S[D - 1] - S[D - 2], dt = tau[D - 1] - tau[D - 2];
+        G += hw * u[D - 1];
+        const double gd = G * (-mu * dS / (dt * dt));
+        gt[D - 1] += gd;
+        gt[D - 2] -= gd;
+    }
+    // inward: profiles, then the reverse sweep from the deepest layer
+    sc_in_mu(D, tau, S, CE, CO, CL, IS);
+    G = 0.0;
+    for (int j = D - 1; j >= 1; --j) {
+        const double Sj = S[j], Sp = S[j - 1];
+        G += hw * u[j];
+        const double e = CE[j], dlw = sc_dlw(e, CL[j], (tau[j] - tau[j - 1]) / mu);
+        const double gx = G * (-IS[j - 1] * e + Sj * e + (Sp - Sj) * dlw) / mu;
+        G *= e;
+        gt[j] += gx;
+        gt[j - 1] -= gx;
+    }
+    {
+        const double t0 = tau[0], S0 = S[0];
+        const double S_top = S0 - t0 * (S[1] - S0) / (tau[1] - t0);
+        double d0, d1;
+        sc_top_dtau(tau, S, d0, d1);
+        G += hw * u[0];
+        const double e = CE[0], lw = CL[0], dlw = sc_dlw(e, lw, t0 / mu);
+        gt[0] += G * (S0 * e + (S_top - S0) * dlw) / mu + G * lw * d0;
+        gt[1] += G * lw * d1;
+    }
+}
+
+// Backward of the total branch for 64 pixels: a workgroup of 64 x 3 threads,
+// threadIdx.y = m the ray direction (called by every thread: it synchronises
+// the workgroup).  Needs the forward's tau, eps, S*, Lambda* and segment tables
+// of the total branch; writes dL/dkappa_line into gk.  A pixel's adjoint
+// iteration stops at max_j |d lambda_j| <= tol max_j |lambda_j| or the cap.
+__device__ inline void dev_reverse_scatter(const StarDev& s, int i) {
+    __shared__ double red[2][3][64];
+    __shared__ int done[64];
+    const int tx = threadIdx.x, m = threadIdx.y, D = s.D;
+    const bool px = i < s.N;
+    const Col B = sc_bcol(s, 0, SC_B, i), tau = sc_bcol(s, 0, SC_TAU, i), eps = sc_bcol(s, 0, SC_EPS, i),
+              S = sc_bcol(s, 0, SC_S, i), Ld = sc_bcol(s, 0, SC_LD, i);
+    const Col CE = sc_bcol(s, 0, SC_CE + m, i), CO = sc_bcol(s, 0, SC_CO + m, i), CL = sc_bcol(s, 0, SC_CL + m, i);
+    const Col lam = sc_col(s, SC_LAM, i), rhs = sc_col(s, SC_RHS, i), IS = sc_col(s, SC_IS + m, i);
+    // per-direction parts: Lambda^T (1 - eps) lambda, dF/dS G, tau terms (continuum-branch columns)
+    // and J* (the total branch's own J parts)
+    const Col U = sc_bcol(s, 1, SC_S, i);
+    const Col Tm[3] = {sc_bcol(s, 1, SC_JM, i), sc_bcol(s, 1, SC_JM + 1, i), sc_bcol(s, 1, SC_JM + 2, i)};
+    const Col gS[3] = {sc_bcol(s, 1, SC_CE, i), sc_bcol(s, 1, SC_CE + 1, i), sc_bcol(s, 1, SC_CE + 2, i)};
+    const Col gt[3] = {sc_bcol(s, 1, SC_CO, i), sc_bcol(s, 1, SC_CO + 1, i), sc_bcol(s, 1, SC_CO + 2, i)};
+    const Col Jm[3] = {sc_bcol(s, 0, SC_JM, i), sc_bcol(s, 0, SC_JM + 1, i), sc_bcol(s, 0, SC_JM + 2, i)};
+    if (px) sc_flux_vjp_mu(D, tau, S, (double)s.dLdF[i], m, CE, CO, CL, IS, gS[m], gt[m]);
+    if (m == 0) done[tx] = px ? 0 : 1;
+    __syncthreads();
+    if (px) {
+        for (int j = m; j < D; j += 3) {
+            const double r = gS[0][j] + gS[1][j] + gS[2][j];
+            rhs[j] = r;
+            lam[j] = r;
+            U[j] = (1.0 - eps[j]) * r;
+        }
+    }
+    __syncthreads();
+    // adjoint fixed point: lambda = rhs + Lambda^T ((1 - eps) lambda)
+    int it = 0;
+    for (;;) {
+        const bool active = px && !done[tx];
+        if (active) sc_lambda_T_mu(D, tau, U, Tm[m], m, CE, CO, CL);
+        __syncthreads();
+        double dmax = 0.0, lmax = 0.0;
+        if (active) {
+            for (int j = m; j < D; j += 3) {
+                const double e = eps[j], lj = lam[j];
+                const double T = Tm[0][j] + Tm[1][j] + Tm[2][j];
+                const double ln = lj + (rhs[j] + T - lj) / (1.0 - (1.0 - e) * Ld[j]);
+                dmax = fmax(dmax, fabs(ln - lj));
+                lmax = fmax(lmax, fabs(ln));
+                lam[j] = ln;
+                U[j] = (1.0 - e) * ln;
+            }
+        }
+        red[0][m][tx] = dmax;
+        red[1][m][tx] = lmax;
+        ++it;
+        __syncthreads();
+        if (m == 0 && active) {
+            const double d = fmax(red[0][0][tx], fmax(red[0][1][tx], red[0][2][tx]));
+            const double l = fmax(red[1][0][tx], fmax(red[1][1][tx], red[1][2][tx]));
+            if (d <= s.sc_tol * l || it >= s.sc_max_iter) {
+                done[tx] = 1;
+                if (s.sc_iters) s.sc_iters[2 * s.Npad + i] = it;
+            }
+        }
+        __syncthreads();
+        if (!__syncthreads_or(!done[tx])) break;
+    }
+    // J* and the tau terms of the fixed point, per direction
+    if (px) {
+        sc_lambda_mu(D, tau, S, Jm[m], m, CE, CO, CL);
+        sc_lambda_tau_vjp_mu(D, tau, S, U, m, CE, CO, CL, IS, gt[m]);
+    }
+    __syncthreads();
+    if (!px || m != 0) return;
     // dL/dchi by the trapezoid adjoint, then dL/dkappa_line
+    const ScPixel p = sc_pixel(s, i);
     const float* kl = s.kappa + i;
     float* out = s.gk + i;
     double suffix = 0.0, gnext = 0.0;
     for (int j = D - 1; j >= 0; --j) {
-        suffix += gt[j];
+        suffix += gt[0][j] + gt[1][j] + gt[2][j];
         double gchi = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
         gchi += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
         gnext = suffix;
         const double sig = s.sigma_c[j] * p.fs;
         const double chi = p.kc + (double)kl[(size_t)j * s.Npad] + sig;
-        const double geps = lam[j] * (B[j] - J[j]);
+        const double geps = lam[j] * (B[j] - (Jm[0][j] + Jm[1][j] + Jm[2][j]));
         out[(size_t)j * s.Npad] = (float)(gchi + geps * sig / (chi * chi));
     }
 }

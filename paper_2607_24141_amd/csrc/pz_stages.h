@@ -298,45 +298,77 @@ __device__ __forceinline__ float planck(const PixelSetup& p, float invT) {
     return p.c1 / expm1f(p.c2 * invT);
 }
 
-__device__ __forceinline__ void dev_flux(const StarDev& s, int i) {
+// A pixel's kappa_line column kappa_line[j][i], read from global memory or
+// from a copy staged in LDS (64 columns interleaved, conflict-free).
+struct GlobalKCol {
+    const float* p;
+    size_t st;
+    __device__ __forceinline__ float operator[](int j) const { return p[(size_t)j * st]; }
+};
+struct LdsKCol {
+    const float* p;
+    __device__ __forceinline__ float operator[](int j) const { return p[j * WAVE]; }
+};
+
+// Copies pixel i's column into col (stride WAVE): sixteen loads in flight per
+// wait instead of one per depth step.  Only the calling thread reads it back.
+__device__ __forceinline__ void stage_kappa_column(const StarDev& s, int i, float* col) {
+    const float* kl = s.kappa + i;
+    const int D = s.D;
+    for (int j0 = 0; j0 < D; j0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = kl[(size_t)min(j0 + u, D - 1) * s.Npad];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (j0 + u < D) col[(j0 + u) * WAVE] = v[u];
+    }
+}
+
+// tau scan and Gauss-3 flux of pixel i on the total branch (TOT: F) and/or
+// the continuum branch (CONT: Fc); both branches share the source function.
+template <bool TOT, bool CONT, class KCol>
+__device__ __forceinline__ void dev_flux(const StarDev& s, int i, const KCol& kl) {
     if (i >= s.N) return;
     const PixelSetup p = pixel_setup(s, i);
     const int D = s.D;
-    const float* kl = s.kappa + i;
-    const size_t st = s.Npad;
     float m0 = (float)s.m[0];
     float S0 = planck(p, (float)(1.0 / s.T[0]));
-    float chi_t = p.kc + kl[0];
+    float chi_t = TOT ? p.kc + kl[0] : 0.0f;
     float tt0 = chi_t * m0;
     float tc0 = p.kc * m0;
     float m1 = (float)s.m[1];
     float S1 = planck(p, (float)(1.0 / s.T[1]));
-    float chi_t1 = p.kc + kl[st];
+    float chi_t1 = TOT ? p.kc + kl[1] : 0.0f;
     float tt1 = fmaf(0.5f * (chi_t + chi_t1), m1 - m0, tt0);
     float tc1 = fmaf(p.kc, m1 - m0, tc0);
     Ray3 rt, rc;
-    rt.top(S0, S1, tt0, tt1);
-    rc.top(S0, S1, tc0, tc1);
+    if (TOT) rt.top(S0, S1, tt0, tt1);
+    if (CONT) rc.top(S0, S1, tc0, tc1);
     float Sa = S0, Sb = S1, ta = tt0, tb = tt1, ca = tc0, cb = tc1;
     float chi_b = chi_t1, mb = m1;
     for (int j = 1; j < D; ++j) {
         if (j > 1) {
             const float mj = (float)s.m[j];
-            const float chi_j = p.kc + kl[(size_t)j * st];
             Sa = Sb;
-            ta = tb;
-            ca = cb;
             Sb = planck(p, (float)(1.0 / s.T[j]));
-            tb = fmaf(0.5f * (chi_b + chi_j), mj - mb, ta);
-            cb = fmaf(p.kc, mj - mb, ca);
-            chi_b = chi_j;
+            if (TOT) {
+                const float chi_j = p.kc + kl[j];
+                ta = tb;
+                tb = fmaf(0.5f * (chi_b + chi_j), mj - mb, ta);
+                chi_b = chi_j;
+            }
+            if (CONT) {
+                ca = cb;
+                cb = fmaf(p.kc, mj - mb, ca);
+            }
             mb = mj;
         }
-        rt.seg(Sa, Sb, ta, tb);
-        rc.seg(Sa, Sb, ca, cb);
+        if (TOT) rt.seg(Sa, Sb, ta, tb);
+        if (CONT) rc.seg(Sa, Sb, ca, cb);
     }
-    s.F[i] = rt.bottom(Sa, Sb, ta, tb);
-    s.Fc[i] = rc.bottom(Sa, Sb, ca, cb);
+    if (TOT) s.F[i] = rt.bottom(Sa, Sb, ta, tb);
+    if (CONT) s.Fc[i] = rc.bottom(Sa, Sb, ca, cb);
 }
 
 // ------------------------------------------------------------ E2 quadrature
@@ -573,8 +605,8 @@ __device__ __forceinline__ ExpTerms64 exp_terms64(double x) {
     return r;
 }
 
-template <int MD>
-__device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i) {
+template <int MD, class KCol>
+__device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i, const KCol& kl) {
     if (i >= s.N) return;
     const int D = s.D;
     const double G = s.dLdF[i];
@@ -590,13 +622,12 @@ __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i) {
     const double l2 = lam_cm * lam_cm;
     const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
     const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
-    const float* kl = s.kappa + i;
     const size_t st = s.Npad;
     // surface quantities
     const double m0 = s.m[0], m1 = s.m[1];
     const double S0 = c1 / expm1(c2 / s.T[0]);
     const double S1 = c1 / expm1(c2 / s.T[1]);
-    const double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[st];
+    const double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[1];
     const double t0 = chi0 * m0;
     const double t1 = t0 + 0.5 * (chi0 + chi1) * (m1 - m0);
     const double dt01 = t1 - t0;
@@ -620,7 +651,7 @@ __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i) {
         if (j + 1 < D) {
             if (j > 0) {
                 const double mj = s.m[j + 1];
-                const double chij = kc + (double)kl[(size_t)(j + 1) * st];
+                const double chij = kc + (double)kl[j + 1];
                 Sa = Sb;
                 ta = tb;
                 Sb = c1 / expm1(c2 / s.T[j + 1]);
