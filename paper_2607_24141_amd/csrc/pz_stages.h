@@ -723,7 +723,7 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 
 // One call per wavefront; l must be wavefront-uniform; pw holds the H and L
-// core tables and lq the line's per-depth parameters lp[l][0..D) (both LDS).
+// core tables and lq the line's rows written by stage_line_params (both LDS).
 // FAM: the damping term is split over the three families by their share of
 // the width at each depth, w_beta = Gamma_beta / Gamma.
 template <bool CT, bool FAM>
@@ -748,14 +748,6 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
             ihi = min(ihi, ic + (int)ceil((dl - log1p(-xl)) / h) + 1);
         }
     }
-    const float xi_f = s.xi[0] * (float)(1.0e10 / (C_LIGHT * C_LIGHT));
-    float gr = 0.0f, gs = 0.0f, gw = 0.0f;
-    if (FAM) {
-        const double4 c = s.lc[l];
-        gr = (float)c.y;
-        gs = (float)c.z;
-        gw = (float)c.w;
-    }
     float sgf = 0.0f, sd = 0.0f, sxi = 0.0f, sds = 0.0f, sdw = 0.0f;
     for (int p0 = ilo; p0 <= ihi; p0 += WPX) {
         const int i = p0 + px;
@@ -772,14 +764,14 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
                     const float gj = g[(size_t)j * s.Npad];
                     float KH, KaHa, KX;
                     voigt_KHD(q.y, q.z, q.w, v, v * v, pw, KH, KaHa, KX);
+                    const float4 e = lp[MAXD + j];
                     sgf = fmaf(gj, KH, sgf);
-                    sxi = fmaf(-gj * KX, xi_f * q.x * q.x, sxi);
+                    sxi = fmaf(gj * KX, e.x, sxi);
                     if (FAM) {
-                        const float Gs = gs * (float)s.ne[j], Gw = gw * (float)s.npert[j];
-                        const float t = gj * KaHa / (gr + Gs + Gw);
-                        sd = fmaf(t, gr, sd);
-                        sds = fmaf(t, Gs, sds);
-                        sdw = fmaf(t, Gw, sdw);
+                        const float t = gj * KaHa;
+                        sd = fmaf(t, e.y, sd);
+                        sds = fmaf(t, e.z, sds);
+                        sdw = fmaf(t, e.w, sdw);
                     } else {
                         sd = fmaf(gj, KaHa, sd);
                     }
@@ -820,11 +812,34 @@ __device__ __forceinline__ void dev_gather(const StarDev& s, int l, int lane, co
     }
 }
 
-// A wavefront copies line l's per-depth parameters to its LDS row (l must be
-// wavefront-uniform; nothing for l >= L).
+// A wavefront copies line l's per-depth parameters to its LDS rows (l must
+// be wavefront-uniform; nothing for l >= L): lq[j] = (c/dv, a^2, K, K a) and
+// lq[MAXD + j] = (-xi (c/dv)^2 per km/s -- the microturbulence factor of the
+// xi term, with its sign -- and, with damping families, the radiative, Stark
+// and van der Waals shares of the width at depth j).
 __device__ __forceinline__ void stage_line_params(const StarDev& s, int l, int lane, float4* lq) {
     if (l >= s.L) return;
-    for (int k = lane; k < s.D; k += WAVE) lq[k] = s.lp[(size_t)l * s.D + k];
+    const float xi_f = s.xi[0] * (float)(1.0e10 / (C_LIGHT * C_LIGHT));
+    float gr = 0.0f, gs = 0.0f, gw = 0.0f;
+    if (s.fam) {
+        const double4 c = s.lc[l];
+        gr = (float)c.y;
+        gs = (float)c.z;
+        gw = (float)c.w;
+    }
+    for (int k = lane; k < s.D; k += WAVE) {
+        const float4 q = s.lp[(size_t)l * s.D + k];
+        lq[k] = q;
+        float4 e = make_float4(-xi_f * q.x * q.x, 0.0f, 0.0f, 0.0f);
+        if (s.fam) {
+            const float Gs = gs * (float)s.ne[k], Gw = gw * (float)s.npert[k];
+            const float inv = 1.0f / (gr + Gs + Gw);
+            e.y = gr * inv;
+            e.z = Gs * inv;
+            e.w = Gw * inv;
+        }
+        lq[MAXD + k] = e;
+    }
 }
 
 // ----------------------------------------------------------- reductions

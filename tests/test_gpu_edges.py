@@ -3,9 +3,10 @@ FP64 oracle: the smallest grid and atmosphere the ABI accepts (N = 2, D = 2,
 one line), the largest depth count (D = 80), strongly damped lines (a from
 0.01 to several thousand: the float64 core and the large-a wings), a jump of
 the perturber density between adjacent layers (a from ~1 to ~3e4 inside one
-wavefront), 200 identical lines in one tile (many LDS chunks), and the
-backward of an empty catalogue (zero abundance and microturbulence
-gradients)."""
+wavefront), damping ratios from ~3 to ~900 over the depths of every line (one
+wing tier for all of a wavefront's depth groups), 200 identical lines in one
+tile (many LDS chunks), and the backward of an empty catalogue (zero
+abundance and microturbulence gradients)."""
 import copy
 
 import numpy as np
@@ -89,6 +90,31 @@ def test_damping_jump_between_layers(gpu_lib):
     err = np.abs(got - ref) / (ref + 1e-6 * kc)
     print("damping jump: max kappa err %.3e" % err.max(), flush=True)
     assert np.all(np.isfinite(got)) and err.max() <= 2e-5
+
+
+def test_wing_tiers_across_depths(gpu_lib):
+    """Damping ratio from ~3 at the top to ~900 at the bottom of 72 depths
+    for every line (not flagged for the wide pass, a < 1000): away from the
+    line centres a wavefront's lanes span |z| from ~5.5 to ~900 over its depth
+    groups, so the opacity kernel sums all of them with one wing tier (the
+    6-node tier up to |z| ~ 900, the 4-node and 2-node tiers farther out)."""
+    import math
+    wl = W.tiny(seed=78, L=30, N=900, D=72, S=3)
+    wl.lines.log_gstark[:] = -14.0
+    p = wl.params
+    dnu = O.line_depth_params(wl.atm, wl.lines, p.dgf, p.ddamp, p.dA, p.xi_kms)["dnu"]
+    wl.lines.log_grad[:] = np.log10(3.0 * 4 * math.pi * dnu[:, 0])
+    wl.lines.log_gvdw[:] = np.log10(900.0 * 4 * math.pi * dnu[:, -1] / wl.atm.npert[-1])
+    a = O.line_depth_params(wl.atm, wl.lines, p.dgf, p.ddamp, p.dA, p.xi_kms)["a"]
+    assert 2.5 < a.min() and a.max() < 1000.0
+    got = _kappa(gpu_lib, wl)
+    ref = O.line_opacity(wl, wl.params)
+    kc = O.continuum_opacity(wl)[None, :]
+    err = np.abs(got - ref) / (ref + 1e-6 * kc)
+    print("wing tiers: max kappa err %.3e" % err.max(), flush=True)
+    assert np.all(np.isfinite(got)) and err.max() <= 2e-5
+    F, Fc = _run_forward(gpu_lib, wl)
+    _flux_close(F, Fc, *O.synthesize(wl))
 
 
 def test_identical_lines_pile_up(gpu_lib):
