@@ -11,7 +11,10 @@
 // Forward: the fixed point S* = eps B + (1 - eps) Lambda S* by accelerated
 // Lambda iteration (Jacobi with the diagonal Lambda*_jj of the same operator):
 //   S <- S + (eps B + (1 - eps) Lambda S - S) / (1 - (1 - eps) Lambda*),
-// from S = B until max_j |dS_j / S_j| <= tol (or the iteration cap), then the
+// from S = B until max_j |dS_j / S_j| <= tol (or the iteration cap), every
+// fourth iteration followed by Ng's extrapolation from the last four iterates
+// (Ng 1974: the combination of them whose next differences are smallest in
+// the relative least-squares sense), then the
 // emergent flux F = 2 pi sum_k w_k mu_k I+(0, mu_k).  Six threads per pixel:
 // the two branches, and in each the three ray directions, which sweep their
 // share of J in parallel and then update a third of the depths each.
@@ -38,12 +41,13 @@ struct Col {
 };
 
 // workspace arrays (each [D][Npad] float64): per branch b (tau, eps, S, Ld, B, the three
-// per-direction parts of J and the segment coefficients of each direction m: e^-x, 1 - e^-x, lw(x)
-// of the segment ending at depth j, j >= 1, and of the surface segment [0, tau_0] at j = 0), then
+// per-direction parts of J, the segment coefficients of each direction m: e^-x, 1 - e^-x, lw(x)
+// of the segment ending at depth j, j >= 1, and of the surface segment [0, tau_0] at j = 0, and
+// the three previous iterates of S), then
 // the backward's lambda, right-hand side and one intensity profile per direction.  The backward
 // keeps its per-direction partial sums in the continuum branch's columns, which it does not need.
 enum { SC_BR = 0, SC_TAU = 0, SC_EPS = 1, SC_S = 2, SC_LD = 3, SC_B = 4, SC_JM = 5, SC_CE = 8, SC_CO = 11,
-       SC_CL = 14, SC_PER_BR = 17, SC_LAM = 34, SC_RHS = 35, SC_IS = 36, SC_NARR = 39 };
+       SC_CL = 14, SC_H = 17, SC_PER_BR = 20, SC_LAM = 40, SC_RHS = 41, SC_IS = 42, SC_NARR = 45 };
 static_assert(SC_NARR == SC_WS_ARRAYS, "scattering workspace size");
 
 __device__ __forceinline__ Col sc_col(const StarDev& s, int id, int i) {
@@ -188,6 +192,56 @@ __device__ inline double sc_flux_mu(int D, const Col& tau, const Col& S, int m, 
     return 2.0 * PI * 2.0 * sc_hw(m) * mu * (I * CE[0] + S_top * CO[0] + (S0 - S_top) * CL[0]);
 }
 
+// Ng's extrapolation of one pixel's S from x0 = S (iterate it) and the
+// previous iterates x1, x2, x3 in H[(it - k) % 3]: with d0 = x0 - x1,
+// d1 = x1 - x2, d2 = x2 - x3 and weights 1/x0^2, (a, b) minimise
+// |d0 - a (d0 - d1) - b (d0 - d2)|^2 and S <- (1 - a - b) x0 + a x1 + b x2;
+// the one-term form (b = 0) when d0 - d1 and d0 - d2 are nearly parallel.
+// Called by every thread of the workgroup (it synchronises it); ng: the
+// pixel is still iterating.  The depth sums are split over the three
+// direction threads and added in a fixed order.
+__device__ inline void sc_ng_step(int D, const Col& S, const Col* H, int it, bool ng, int m, int tx,
+                                  double (*ngs)[3][64]) {
+    const Col &h1 = H[(it - 1) % 3], &h2 = H[(it - 2) % 3], &h3 = H[(it - 3) % 3];
+    double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ng) {
+        for (int j = m; j < D; j += 3) {
+            const double x0 = S[j], x1 = h1[j], x2 = h2[j], x3 = h3[j];
+            const double d0 = x0 - x1, u = d0 - (x1 - x2), v = d0 - (x2 - x3), w = 1.0 / (x0 * x0);
+            p[0] += w * u * u;
+            p[1] += w * u * v;
+            p[2] += w * v * v;
+            p[3] += w * d0 * u;
+            p[4] += w * d0 * v;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ngs[k][m][tx] = p[k];
+    __syncthreads();
+    if (m == 0 && ng) {
+        double q[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) q[k] = ngs[k][0][tx] + ngs[k][1][tx] + ngs[k][2][tx];
+        const double det = q[0] * q[2] - q[1] * q[1];
+        double a = 0.0, c = 0.0;
+        if (det > 1e-10 * q[0] * q[2]) {
+            a = (q[3] * q[2] - q[4] * q[1]) / det;
+            c = (q[4] * q[0] - q[3] * q[1]) / det;
+        } else if (q[0] > 0.0) {
+            a = q[3] / q[0];
+        }
+        if (!(isfinite(a) && isfinite(c))) a = c = 0.0;
+        ngs[0][0][tx] = a;
+        ngs[1][0][tx] = c;
+    }
+    __syncthreads();
+    if (ng) {
+        const double a = ngs[0][0][tx], c = ngs[1][0][tx];
+        for (int j = m; j < D; j += 3) S[j] = (1.0 - a - c) * S[j] + a * h1[j] + c * h2[j];
+    }
+    __syncthreads();
+}
+
 // Forward of one branch for 64 pixels: a workgroup of 64 x 3 threads,
 // threadIdx.y = m the ray direction (called by every thread: it synchronises
 // the workgroup).  Each iteration every direction sweeps into its part of J;
@@ -196,6 +250,7 @@ __device__ inline double sc_flux_mu(int D, const Col& tau, const Col& S, int m, 
 // its result does not depend on the other pixels of the workgroup.
 __device__ inline void dev_flux_scatter(const StarDev& s, int i, int b) {
     __shared__ double red[3][64];
+    __shared__ double ngs[5][3][64];
     __shared__ int done[64];
     const int tx = threadIdx.x, m = threadIdx.y, D = s.D;
     const bool px = i < s.N;
@@ -205,6 +260,7 @@ __device__ inline void dev_flux_scatter(const StarDev& s, int i, int b) {
     const Col CE[3] = {sc_bcol(s, b, SC_CE, i), sc_bcol(s, b, SC_CE + 1, i), sc_bcol(s, b, SC_CE + 2, i)};
     const Col CO[3] = {sc_bcol(s, b, SC_CO, i), sc_bcol(s, b, SC_CO + 1, i), sc_bcol(s, b, SC_CO + 2, i)};
     const Col CL[3] = {sc_bcol(s, b, SC_CL, i), sc_bcol(s, b, SC_CL + 1, i), sc_bcol(s, b, SC_CL + 2, i)};
+    const Col H[3] = {sc_bcol(s, b, SC_H, i), sc_bcol(s, b, SC_H + 1, i), sc_bcol(s, b, SC_H + 2, i)};
     if (px && m == 0) sc_setup(s, i, b, sc_pixel(s, i));
     if (m == 0) done[tx] = px ? 0 : 1;
     __syncthreads();
@@ -218,11 +274,13 @@ __device__ inline void dev_flux_scatter(const StarDev& s, int i, int b) {
         __syncthreads();
         double dmax = 0.0;
         if (active) {
+            const Col& Hs = H[it % 3];                // iterate `it` becomes history
             for (int j = m; j < D; j += 3) {
                 const double e = eps[j], Sj = S[j];
                 const double J = Jm[0][j] + Jm[1][j] + Jm[2][j];
                 const double Sn = Sj + (e * B[j] + (1.0 - e) * J - Sj) / (1.0 - (1.0 - e) * Ld[j]);
                 dmax = fmax(dmax, fabs(Sn - Sj) / fabs(Sn));
+                Hs[j] = Sj;
                 S[j] = Sn;
             }
         }
@@ -237,6 +295,7 @@ __device__ inline void dev_flux_scatter(const StarDev& s, int i, int b) {
             }
         }
         __syncthreads();
+        if (it % 4 == 0) sc_ng_step(D, S, H, it, px && !done[tx], m, tx, ngs);
         if (!__syncthreads_or(!done[tx])) break;
     }
     const double f = px ? sc_flux_mu(D, tau, S, m, CE[m], CO[m], CL[m]) : 0.0;
