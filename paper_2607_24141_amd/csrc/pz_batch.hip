@@ -92,8 +92,9 @@ __global__ __launch_bounds__(512) void kb_params(const StarDev* __restrict__ sta
     }
 }
 
-// ANYCT: some star of the batch uses the centre test (the LDS holds its rows).
-template <int WPX, bool ANYCT>
+// ANYCT: some star of the batch uses the centre test (the LDS holds its rows);
+// G: depth-group slots (at least D / (64 / WPX) for every star).
+template <int WPX, bool ANYCT, int G>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     __shared__ OpacityLds<WPX, ANYCT> sm;
     __shared__ int s_it;
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const St
         if (it >= n) return;
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, false, ANYCT>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, false, ANYCT, G>(s, w.y, s.chunk, sm);
     }
 }
 
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity_wide(con
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, true, ANYCT>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, true, ANYCT, opacity_max_groups<WPX>()>(s, w.y, s.chunk, sm);
     }
 }
 
@@ -225,9 +226,9 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <bool ANYCT>
 static hipError_t batch_opacity_occupancy(int* occ) {
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], kb_opacity<4, ANYCT>, 512, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], kb_opacity<8, ANYCT>, 512, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], kb_opacity<16, ANYCT>, 512, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], kb_opacity<4, ANYCT, 4>, 512, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], kb_opacity<8, ANYCT, 9>, 512, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], kb_opacity<16, ANYCT, 19>, 512, 0);
     return e;
 }
 
@@ -236,6 +237,7 @@ struct pz_batch {
     int device;
     bool has_target;
     bool any_center;      // some star uses the centre test
+    int max_d;            // largest depth count of the stars
     std::vector<const pz_plan*> plans;
     int n_items[N_PHASE];
     int2* items[N_PHASE];
@@ -248,26 +250,28 @@ struct pz_batch {
     void* base;
 };
 
+// One phase's opacity launches: the main pass with the fewest depth-group
+// slots that hold every star's D / (64 / WPX) groups, then the wide pass.
+template <int WPX, bool ANYCT>
+static void batch_opacity_wpx(const pz_batch* bt, int n, const int2* items, int* ctr, int grid, hipStream_t st) {
+    constexpr int GB = opacity_max_groups<WPX>();
+    if (bt->max_d / (64 / WPX) < GB)
+        kb_opacity<WPX, ANYCT, GB - 1><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
+    else
+        kb_opacity<WPX, ANYCT, GB><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
+    kb_opacity_wide<WPX, ANYCT><<<grid, 512, 0, st>>>(bt->stars, items, n);
+}
+
 template <bool ANYCT>
 static void batch_opacity(const pz_batch* bt, hipStream_t st) {
     auto grid = [](int want, int n) { return std::max(1, std::min(want, n)); };
     const int* n = bt->n_items;
     int2* const* it = bt->items;
-    if (n[PH_OP32]) {
-        kb_opacity<4, ANYCT><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32], bt->ctr);
-        kb_opacity_wide<4, ANYCT><<<grid(bt->grid_op[0], n[PH_OP32]), 512, 0, st>>>(bt->stars, it[PH_OP32], n[PH_OP32]);
-    }
-    if (n[PH_OP64]) {
-        kb_opacity<8, ANYCT><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64],
-                                                                             bt->ctr + 1);
-        kb_opacity_wide<8, ANYCT><<<grid(bt->grid_op[1], n[PH_OP64]), 512, 0, st>>>(bt->stars, it[PH_OP64], n[PH_OP64]);
-    }
-    if (n[PH_OP128]) {
-        kb_opacity<16, ANYCT><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128], n[PH_OP128],
-                                                                               bt->ctr + 2);
-        kb_opacity_wide<16, ANYCT><<<grid(bt->grid_op[2], n[PH_OP128]), 512, 0, st>>>(bt->stars, it[PH_OP128],
-                                                                                    n[PH_OP128]);
-    }
+    if (n[PH_OP32]) batch_opacity_wpx<4, ANYCT>(bt, n[PH_OP32], it[PH_OP32], bt->ctr, grid(bt->grid_op[0], n[PH_OP32]), st);
+    if (n[PH_OP64])
+        batch_opacity_wpx<8, ANYCT>(bt, n[PH_OP64], it[PH_OP64], bt->ctr + 1, grid(bt->grid_op[1], n[PH_OP64]), st);
+    if (n[PH_OP128])
+        batch_opacity_wpx<16, ANYCT>(bt, n[PH_OP128], it[PH_OP128], bt->ctr + 2, grid(bt->grid_op[2], n[PH_OP128]), st);
 }
 
 extern "C" {
@@ -373,7 +377,11 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
     int n_cu = 0, occ_op[3] = {0, 0, 0}, occ_g = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, bt->device);
     bt->any_center = false;
-    for (int b = 0; b < n_star; ++b) bt->any_center = bt->any_center || sd[b].center;
+    bt->max_d = 0;
+    for (int b = 0; b < n_star; ++b) {
+        bt->any_center = bt->any_center || sd[b].center;
+        bt->max_d = std::max(bt->max_d, sd[b].D);
+    }
     if (e == hipSuccess)
         e = bt->any_center ? batch_opacity_occupancy<true>(occ_op) : batch_opacity_occupancy<false>(occ_op);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_g, kb_gather, 512, 0);

@@ -27,8 +27,9 @@ __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
 // (longest-processing-time first): tiles differ several-fold in line count
 // (band clusters), and a one-shot grid of ~N/TPX workgroups leaves a long
 // tail of heavy tiles.
-// CT: the plan uses the centre test (its LDS holds the zmax rows).
-template <int WPX, bool CT>
+// CT: the plan uses the centre test (its LDS holds the zmax rows); G: depth-group
+// slots per lane (at least D / (64 / WPX)).
+template <int WPX, bool CT, int G>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
     __shared__ OpacityLds<WPX, CT> sm;
     __shared__ int s_it;
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
         const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= s.n_tiles) return;
-        dev_opacity_tile<WPX, false, CT>(s, s.tile_order[it], chunk, sm);
+        dev_opacity_tile<WPX, false, CT, G>(s, s.tile_order[it], chunk, sm);
     }
 }
 
@@ -50,7 +51,8 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity_wide(Star
     if (s.wide_any[0] == 0) return;                   // the usual case: no flagged line
     load_pw_table(sm.pw, false);
     __syncthreads();
-    for (int t = blockIdx.x; t < s.n_tiles; t += gridDim.x) dev_opacity_tile<WPX, true, CT>(s, t, chunk, sm);
+    for (int t = blockIdx.x; t < s.n_tiles; t += gridDim.x)
+        dev_opacity_tile<WPX, true, CT, opacity_max_groups<WPX>()>(s, t, chunk, sm);
 }
 
 __global__ void k_reset_queue(int* ctr) { ctr[0] = 0; }
@@ -63,9 +65,9 @@ __global__ __launch_bounds__(256) void k_select(StarDev s, double eta, double bi
 template <bool CT>
 static hipError_t opacity_occupancy(int tile_px, int* occ) {
     switch (tile_px) {
-        case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<4, CT>, 512, 0);
-        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<8, CT>, 512, 0);
-        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<16, CT>, 512, 0);
+        case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<4, CT, 4>, 512, 0);
+        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<8, CT, 9>, 512, 0);
+        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<16, CT, 19>, 512, 0);
     }
 }
 
@@ -206,21 +208,24 @@ hipError_t launch_line_params(const StarDev& s, hipStream_t st) {
     return hipGetLastError();
 }
 
+// The main pass with the fewest depth-group slots that hold D / (64 / WPX)
+// groups, then the wide pass.
+template <int WPX, bool CT>
+static void launch_opacity_wpx(const StarDev& s, int chunk, int grid, hipStream_t st) {
+    constexpr int GB = opacity_max_groups<WPX>();
+    if (s.D / (64 / WPX) < GB)
+        k_opacity<WPX, CT, GB - 1><<<grid, 512, 0, st>>>(s, chunk);
+    else
+        k_opacity<WPX, CT, GB><<<grid, 512, 0, st>>>(s, chunk);
+    k_opacity_wide<WPX, CT><<<grid, 512, 0, st>>>(s, chunk);
+}
+
 template <bool CT>
 static hipError_t launch_opacity_tiles(const StarDev& s, int chunk, int grid, hipStream_t st) {
     switch (s.tile_px) {
-        case 32:
-            k_opacity<4, CT><<<grid, 512, 0, st>>>(s, chunk);
-            k_opacity_wide<4, CT><<<grid, 512, 0, st>>>(s, chunk);
-            break;
-        case 64:
-            k_opacity<8, CT><<<grid, 512, 0, st>>>(s, chunk);
-            k_opacity_wide<8, CT><<<grid, 512, 0, st>>>(s, chunk);
-            break;
-        case 128:
-            k_opacity<16, CT><<<grid, 512, 0, st>>>(s, chunk);
-            k_opacity_wide<16, CT><<<grid, 512, 0, st>>>(s, chunk);
-            break;
+        case 32: launch_opacity_wpx<4, CT>(s, chunk, grid, st); break;
+        case 64: launch_opacity_wpx<8, CT>(s, chunk, grid, st); break;
+        case 128: launch_opacity_wpx<16, CT>(s, chunk, grid, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

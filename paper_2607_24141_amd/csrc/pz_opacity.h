@@ -148,10 +148,16 @@ __device__ __forceinline__ void wing_sums(float* acc, const float4* pd, const fl
 // With the centre test (CT) a pixel's detuning is marked kNoLine beyond the
 // line's largest span, and a (pixel, depth) lane evaluates only where
 // v^2 + a^2 <= zmax of its (line, depth).
-template <int WPX, bool CT, bool WIDE, class Lds>
+// Depth-group slots of a lane: G >= D / NDG full groups (the launch takes
+// the smallest instantiation that holds them; fewer slots, fewer registers).
+template <int WPX>
+constexpr int opacity_max_groups() { return MAXD / (64 / WPX); }
+
+template <int WPX, bool CT, bool WIDE, int G, class Lds>
 __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, Lds& sm) {
     constexpr int NDG = 64 / WPX;
-    constexpr int DPT = MAXD / NDG;                    // most full depth groups
+    constexpr int DPT = G;                             // depth-group slots (>= full groups)
+    static_assert(G >= 1 && G <= MAXD / NDG, "depth-group slots");
     constexpr int TPX = 8 * WPX;
     const int tid = threadIdx.x;
     const int lane = tid % 64;
@@ -277,12 +283,13 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 // far wing tiers across depths) with the evaluator that keeps each lane on
 // its own tier.  ANYCT: the workgroup's LDS has the centre test's rows, so
 // stars with the centre test are taken too.
-template <int WPX, bool WIDE, bool ANYCT>
+// G: depth-group slots, at least the star's D / NDG.
+template <int WPX, bool WIDE, bool ANYCT, int G>
 __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX, ANYCT>& sm) {
     if (ANYCT && s.center)
-        opacity_tile_body<WPX, ANYCT, WIDE>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, ANYCT, WIDE, G>(s, tile, chunk, sm);
     else
-        opacity_tile_body<WPX, false, WIDE>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, false, WIDE, G>(s, tile, chunk, sm);
 }
 
 }  // namespace pz
