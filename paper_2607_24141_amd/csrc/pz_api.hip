@@ -110,6 +110,8 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     if (n_depth < 2 || n_depth > PZ_MAX_DEPTH)
         return fail(PZ_E_SHAPE, "n_depth must be in [2, %d] (got %d)", PZ_MAX_DEPTH, n_depth);
     if (lines->L < 0) return fail(PZ_E_SHAPE, "L must be >= 0");
+    if ((long long)lines->L * n_depth >= (1LL << 31))
+        return fail(PZ_E_SHAPE, "L x n_depth must be below 2^31 (got %lld)", (long long)lines->L * n_depth);
     if (!(opts->window_nm > 0.0) || !std::isfinite(opts->window_nm))
         return fail(PZ_E_INVALID_ARG, "window_nm must be finite and > 0");
     if (opts->quadrature != PZ_QUAD_GAUSS3 && opts->quadrature != PZ_QUAD_E2)

@@ -156,18 +156,18 @@ __device__ __forceinline__ void dev_line_consts(const StarDev& s, int l, double3
 // Every lane of the wavefront must call this (lanes past L*D included):
 // the centre test reduces across the wavefront.
 __device__ __forceinline__ void dev_line_params(const StarDev& s, long idx) {
-    const long n = (long)s.L * s.D;
+    const long n = (long)s.L * s.D;                       // < 2^32 (the plan checks L D)
     const bool valid = idx < n;
-    const long id = valid ? idx : n - 1;                  // out-of-range lanes compute a copy, store nothing
-    const int l = (int)(id / s.D), j = (int)(id - (long)l * s.D);
+    const unsigned id = (unsigned)(valid ? idx : n - 1);  // out-of-range lanes compute a copy, store nothing
+    const int l = (int)(id / (unsigned)s.D), j = (int)(id - (unsigned)l * (unsigned)s.D);
     const double T = s.T[j];
     const int spion = s.ln.spion[l];
     const double inv_dv = s.inv_dv[(spion >> 1) * s.D + j];
     const double4 c = s.lc[l];
     const double a = fma(c.w, s.npert[j], fma(c.z, s.ne[j], c.y)) * inv_dv;
-    const double kT = K_BOLTZ * T;
-    const double K = c.x * s.pop[spion * s.D + j] * exp(-s.ln.E_eV[l] * EV_ERG / kT) *
-                     (-expm1(-H_PLANCK * C_LIGHT / (s.ln.lam_cm[l] * kT))) * inv_dv;
+    const double ikT = 1.0 / (K_BOLTZ * T);
+    const double K = c.x * s.pop[spion * s.D + j] * exp(-s.ln.E_eV[l] * EV_ERG * ikT) *
+                     (-expm1(-(H_PLANCK * C_LIGHT) / s.ln.lam_cm[l] * ikT)) * inv_dv;
     if (valid) s.lp[idx] = make_float4((float)(C_LIGHT * inv_dv), (float)(a * a), (float)K, (float)(K * a));
     if (!s.center) return;
     // continuum-referenced centre test, decided in float64: keep iff
