@@ -155,7 +155,7 @@ __global__ __launch_bounds__(1024) void kb_loss(const StarDev* __restrict__ star
 }
 
 __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
-    __shared__ float kst[MAXD * WAVE];                // each thread's own kappa_line column
+    __shared__ double col[MAXD * WAVE];               // each thread's own column
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
@@ -163,8 +163,8 @@ __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ sta
         if (s.quad == PZ_QUAD_E2) {
             dev_reverse_scan_e2<MAXD>(s, i);
         } else {
-            if (i < s.N) stage_kappa_column(s, i, kst + threadIdx.x);
-            dev_reverse_scan<MAXD>(s, i, LdsKCol{kst + threadIdx.x});
+            if (i < s.N) stage_kappa_column64(s, i, col + threadIdx.x);
+            dev_reverse_scan(s, i, col + threadIdx.x);
         }
     }
 }

@@ -139,12 +139,12 @@ __global__ void k_debug_formal(int D, int n, const float* S, const float* tau, i
     F[i] = r.bottom(Sa, Sb, ta, tb);
 }
 
-template <int MD>
+// One thread per pixel; its float64 column in LDS holds kappa_line, then dL/dtau.
 __global__ __launch_bounds__(64) void k_reverse_scan(StarDev s) {
-    __shared__ float kst[MD * WAVE];
+    __shared__ double col[MAXD * WAVE];
     const int i = blockIdx.x * WAVE + threadIdx.x;
-    if (i < s.N) stage_kappa_column(s, i, kst + threadIdx.x);
-    dev_reverse_scan<MD>(s, i, LdsKCol{kst + threadIdx.x});
+    if (i < s.N) stage_kappa_column64(s, i, col + threadIdx.x);
+    dev_reverse_scan(s, i, col + threadIdx.x);
 }
 
 template <int MD>
@@ -254,7 +254,7 @@ hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st) {
     else if (s.quad == PZ_QUAD_E2)
         k_reverse_scan_e2<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else
-        k_reverse_scan<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
+        k_reverse_scan<<<(s.N + 63) / 64, 64, 0, st>>>(s);
     return hipGetLastError();
 }
 

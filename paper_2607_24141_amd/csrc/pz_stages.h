@@ -605,16 +605,30 @@ __device__ __forceinline__ ExpTerms64 exp_terms64(double x) {
     return r;
 }
 
-template <int MD, class KCol>
-__device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i, const KCol& kl) {
+// Pixel i's column of a workgroup of WAVE pixels: col[j * WAVE], float64 in
+// LDS.  On entry it holds kappa_line[j][i]; the scan overwrites slot j with
+// dL/dtau_j once kappa_line[j] has been read (each slot is written once: the
+// term a segment adds to the next depth is carried in a register), then the
+// trapezoid adjoint runs up from the bottom.
+__device__ __forceinline__ void stage_kappa_column64(const StarDev& s, int i, double* col) {
+    const float* kl = s.kappa + i;
+    const int D = s.D;
+    for (int j0 = 0; j0 < D; j0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = kl[(size_t)min(j0 + u, D - 1) * s.Npad];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (j0 + u < D) col[(j0 + u) * WAVE] = (double)v[u];
+    }
+}
+
+__device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i, double* col) {
     if (i >= s.N) return;
     const int D = s.D;
     const double G = s.dLdF[i];
     const double mu[3] = {kMu0, kMu1, kMu2};
     const double wmu[3] = {2.0 * PI * 5.0 / 18.0 * kMu0, 2.0 * PI * 8.0 / 18.0 * kMu1, 2.0 * PI * 5.0 / 18.0 * kMu2};
-    double gt[MD];
-#pragma unroll
-    for (int j = 0; j < MD; ++j) gt[j] = 0.0;
     // pixel constants in float64
     const double lnl = log(s.lam_first_nm) + (double)i * s.h;
     const double lam_cm = exp(lnl) * 1.0e-7;
@@ -622,57 +636,58 @@ __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i, const 
     const double l2 = lam_cm * lam_cm;
     const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
     const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
-    const size_t st = s.Npad;
     // surface quantities
     const double m0 = s.m[0], m1 = s.m[1];
     const double S0 = c1 / expm1(c2 / s.T[0]);
     const double S1 = c1 / expm1(c2 / s.T[1]);
-    const double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[1];
+    const double chi0 = kc + col[0], chi1 = kc + col[WAVE];
     const double t0 = chi0 * m0;
     const double t1 = t0 + 0.5 * (chi0 + chi1) * (m1 - m0);
     const double dt01 = t1 - t0;
     const double sig = (S1 - S0) / dt01;
     const double S_top = S0 - t0 * sig;
-    double A[3];
+    double A[3], g0 = 0.0, g1 = 0.0;                    // surface terms of dL/dtau_0, dL/dtau_1
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double Gk = G * wmu[k];
         const ExpTerms64 et = exp_terms64(t0 / mu[k]);
         const double dCdx = S_top * et.e + (S0 - S_top) * et.dlw;
         const double dCdS = et.om - et.lw;
-        gt[0] += Gk * (dCdx / mu[k] + dCdS * (-sig - t0 * sig / dt01));
-        gt[1] += Gk * dCdS * (t0 * sig / dt01);
+        g0 += Gk * (dCdx / mu[k] + dCdS * (-sig - t0 * sig / dt01));
+        g1 += Gk * dCdS * (t0 * sig / dt01);
         A[k] = et.e;
     }
-    // segments
+    // segments [j, j + 1]: ga to dL/dtau_j, gb to dL/dtau_{j+1}
     double Sa = S0, Sb = S1, ta = t0, tb = t1, chib = chi1, mb = m1;
-#pragma unroll
-    for (int j = 0; j < MD - 1; ++j) {
-        if (j + 1 < D) {
-            if (j > 0) {
-                const double mj = s.m[j + 1];
-                const double chij = kc + (double)kl[j + 1];
-                Sa = Sb;
-                ta = tb;
-                Sb = c1 / expm1(c2 / s.T[j + 1]);
-                tb = ta + 0.5 * (chib + chij) * (mj - mb);
-                chib = chij;
-                mb = mj;
-            }
-            double ga = 0.0, gb = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const ExpTerms64 et = exp_terms64((tb - ta) / mu[k]);
-                const double c = Sa * et.om + (Sb - Sa) * et.lw;
-                const double dc = Sa * et.e + (Sb - Sa) * et.dlw;
-                const double w = G * wmu[k] * A[k] / mu[k];
-                ga -= w * (c + dc);
-                gb += w * dc;
-                A[k] *= et.e;
-            }
-            gt[j] += ga;
-            gt[j + 1] += gb;
+    double pend = g1, last = 0.0;                      // pend: what depth j already holds
+    for (int j = 0; j < D - 1; ++j) {
+        if (j > 0) {
+            const double mj = s.m[j + 1];
+            const double chij = kc + col[(j + 1) * WAVE];
+            Sa = Sb;
+            ta = tb;
+            Sb = c1 / expm1(c2 / s.T[j + 1]);
+            tb = ta + 0.5 * (chib + chij) * (mj - mb);
+            chib = chij;
+            mb = mj;
         }
+        double ga = 0.0, gb = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const ExpTerms64 et = exp_terms64((tb - ta) / mu[k]);
+            const double c = Sa * et.om + (Sb - Sa) * et.lw;
+            const double dc = Sa * et.e + (Sb - Sa) * et.dlw;
+            const double w = G * wmu[k] * A[k] / mu[k];
+            ga -= w * (c + dc);
+            gb += w * dc;
+            A[k] *= et.e;
+        }
+        const double gj = (j == 0 ? g0 : pend) + ga;   // depth j is complete but for the bottom term
+        if (j < D - 2)
+            col[j * WAVE] = gj;
+        else
+            last = gj;
+        pend = j == 0 ? g1 + gb : gb;
     }
     // bottom boundary (Sa, Sb, ta, tb are now the last segment)
     {
@@ -686,24 +701,19 @@ __device__ __forceinline__ void dev_reverse_scan(const StarDev& s, int i, const 
             g_last += Gk * (-ID / mu[k] - q);
             g_prev += Gk * q;
         }
-#pragma unroll
-        for (int j = 0; j < MD; ++j) {
-            if (j == D - 1) gt[j] += g_last;
-            if (j == D - 2) gt[j] += g_prev;
-        }
+        col[(D - 2) * WAVE] = last + g_prev;
+        col[(D - 1) * WAVE] = pend + g_last;
     }
     // dL/dchi_j from the trapezoid rule via suffix sums
     double suffix = 0.0, gnext = 0.0;
     float* out = s.gk + i;
-#pragma unroll
-    for (int j = MD - 1; j >= 0; --j) {
-        if (j < D) {
-            suffix += gt[j];
-            double g = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
-            g += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
-            out[(size_t)j * st] = (float)g;
-            gnext = suffix;
-        }
+    const size_t st = s.Npad;
+    for (int j = D - 1; j >= 0; --j) {
+        suffix += col[j * WAVE];
+        double g = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
+        g += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
+        out[(size_t)j * st] = (float)g;
+        gnext = suffix;
     }
 }
 
