@@ -120,7 +120,7 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
     if (tile_px != 32 && tile_px != 64 && tile_px != 128)
         return fail(PZ_E_INVALID_ARG, "tile_px must be 0, 32, 64 or 128 (got %d)", opts->tile_px);
     int chunk = opts->lines_per_chunk ? opts->lines_per_chunk : 16;
-    if (chunk < 1 || chunk > 16) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, 16]");
+    if (chunk < 1 || chunk > MAX_CHUNK) return fail(PZ_E_INVALID_ARG, "lines_per_chunk must be in [0, %d]", MAX_CHUNK);
     if (opts->flags & ~(PZ_FLAG_DAMPING_FAMILIES | PZ_FLAG_SCATTERING))
         return fail(PZ_E_INVALID_ARG, "unknown bits in flags");
     if (opts->scatter_max_iter < 0 || opts->scatter_max_iter > 100000)

@@ -106,6 +106,7 @@ struct StarDev {
 
 static constexpr int RCHUNK = 2048;      // lines per reduction partial
 static constexpr int SC_WS_ARRAYS = 45;  // [D][Npad] float64 arrays of the scattering workspace
+static constexpr int MAX_CHUNK = 16;     // most lines per LDS chunk of the opacity tile
 
 // Kernel launchers (pz_kernels.hip).  Each enqueues on the stream and returns
 // the hipError_t of the launch.

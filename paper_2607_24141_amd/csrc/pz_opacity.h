@@ -39,7 +39,6 @@ __device__ __forceinline__ float detuning(int k, float delta, float h_hi, float 
 // to the first wavefronts 64 at a time (pixel t / r, depth nfull NDG + t % r).
 // No atomics: every (pixel, depth) sum is owned by one thread and runs in a
 // fixed line order (chunk by chunk).
-static constexpr int MAX_CHUNK = 16;
 static constexpr float kNoLine = 2.0f;
 
 // Resident wavefronts per SIMD.  Six for 4-pixel wavefronts: the 80 VGPRs
