@@ -7,14 +7,15 @@ one whole forward synthesis (populations, line parameters, windowed Voigt
 opacity, depth scan and Gauss-3 flux for both branches).  Extra fields: the
 forward+backward step (chi^2 loss seed and the adjoint for all 4e5 + 20 + 1
 corrections), the centre test, continuum scattering (the source function
-iterated to its fixed point, forward and forward+backward), the line-selection keep test (and the forward
-of its kept subset), the instrument operator, the line calibration
+iterated to its fixed point, forward and forward+backward), the exact E2
+angle integral instead of Gauss-3, the line-selection keep test (and the
+forward of its kept subset), the instrument operator, the line calibration
 (objective evaluation and L-BFGS updates over 25,147 correction groups of a
 two-star, three-spectrum fit) and the batched launch over 256 stars, the roofline of the
 dominant kernel (opacity) and the FP64 CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                      [--modes fwd,fwdbwd,center,select,scatter,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
+                      [--modes fwd,fwdbwd,center,select,scatter,e2,instrument,calibration,batch] [--cal-updates 40] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -114,7 +115,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="fwd,fwdbwd,center,select,scatter,instrument,calibration,batch")
+    ap.add_argument("--modes", default="fwd,fwdbwd,center,select,scatter,e2,instrument,calibration,batch")
     ap.add_argument("--cal-updates", type=int, default=40, help="L-BFGS updates of the calibration block")
     ap.add_argument("--batch-stars", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
@@ -301,6 +302,37 @@ def main():
                              "max_iterations_adjoint": int(it_b[2]),
                              "stage_ms_fwd_bwd": {k: (v[0] / max(v[1], 1)) for k, v in sprof_b.items() if v[1]}}
         splan.destroy()
+
+    # ---- the same workload with the exact E2 angle integral (float64 transfer)
+    if "e2" in modes:
+        import copy
+        ewl = copy.copy(wl)
+        ewl.quadrature = "e2"
+        eplan = pz.plan_for(ewl, tile_px=plan.tile_px)
+        efwd = lambda: pz.synth_forward(eplan, atm, par, F, Fc)
+        eplan.profile(True)
+        ms_ef, _ = timed(efwd, args.steps, args.warmup, torch)
+        eprof = eplan.profile_read()
+        eplan.profile(False)
+        egF = torch.empty_like(F)
+        eg = [torch.empty(L, device=dev), torch.empty(L, device=dev), torch.empty(S, device=dev),
+              torch.empty(1, device=dev)]
+        eys = torch.ones_like(F)
+
+        def efb():
+            pz.synth_forward(eplan, atm, par, F, Fc)
+            pz.pz_chi2_seed(F, Fc, eys, 0.01, egF, None, None)
+            pz.synth_backward(eplan, atm, par, egF, *eg)
+
+        eplan.profile(True)
+        ms_efb, _ = timed(efb, args.steps, args.warmup, torch)
+        eprof_b = eplan.profile_read()
+        eplan.profile(False)
+        out["e2"] = {"fwd_spectra_per_s": 1000.0 / ms_ef, "fwd_ms": ms_ef,
+                     "fwd_bwd_spectra_per_s": 1000.0 / ms_efb, "fwd_bwd_ms": ms_efb,
+                     "stage_ms_fwd": {k: (v[0] / max(v[1], 1)) for k, v in eprof.items() if v[1]},
+                     "stage_ms_fwd_bwd": {k: (v[0] / max(v[1], 1)) for k, v in eprof_b.items() if v[1]}}
+        eplan.destroy()
 
     # ---- the instrument operator of Eq. 31 on APOGEE-like pixels (one flux pair)
     if "instrument" in modes:

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(512) void kb_flux(const StarDev* __restrict__ stars
         const StarDev& s = stars[w.x];
         const int i = w.y * 512 + threadIdx.x;
         if (s.quad == PZ_QUAD_E2)
-            dev_flux_e2(s, i);
+            dev_flux_e2<true, true>(s, i, GlobalKCol{s.kappa + i, (size_t)s.Npad});
         else
             dev_flux<true, true>(s, i, GlobalKCol{s.kappa + i, (size_t)s.Npad});
     }
@@ -161,7 +161,8 @@ __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ sta
         const StarDev& s = stars[w.x];
         const int i = w.y * 64 + threadIdx.x;
         if (s.quad == PZ_QUAD_E2) {
-            dev_reverse_scan_e2<MAXD>(s, i);
+            if (i < s.N) stage_kappa_column64(s, i, col + threadIdx.x);
+            dev_reverse_scan_e2(s, i, col + threadIdx.x);
         } else {
             if (i < s.N) stage_kappa_column64(s, i, col + threadIdx.x);
             dev_reverse_scan(s, i, col + threadIdx.x);

@@ -93,7 +93,17 @@ __global__ __launch_bounds__(64) void k_flux(StarDev s) {
     }
 }
 
-__global__ __launch_bounds__(64) void k_flux_e2(StarDev s) { dev_flux_e2(s, blockIdx.x * blockDim.x + threadIdx.x); }
+// As k_flux, with the exact E2 angle integral in float64.
+__global__ __launch_bounds__(64) void k_flux_e2(StarDev s) {
+    __shared__ float kst[MAXD * WAVE];
+    const int i = blockIdx.x * WAVE + threadIdx.x;
+    if (blockIdx.y == 0) {
+        if (i < s.N) stage_kappa_column(s, i, kst + threadIdx.x);
+        dev_flux_e2<true, false>(s, i, LdsKCol{kst + threadIdx.x});
+    } else {
+        dev_flux_e2<false, true>(s, i, GlobalKCol{s.kappa + i, (size_t)s.Npad});
+    }
+}
 
 __global__ __launch_bounds__(192) void k_flux_scatter(StarDev s) {
     dev_flux_scatter(s, blockIdx.x * 64 + threadIdx.x, blockIdx.y);
@@ -147,9 +157,11 @@ __global__ __launch_bounds__(64) void k_reverse_scan(StarDev s) {
     dev_reverse_scan(s, i, col + threadIdx.x);
 }
 
-template <int MD>
 __global__ __launch_bounds__(64) void k_reverse_scan_e2(StarDev s) {
-    dev_reverse_scan_e2<MD>(s, blockIdx.x * blockDim.x + threadIdx.x);
+    __shared__ double col[MAXD * WAVE];
+    const int i = blockIdx.x * WAVE + threadIdx.x;
+    if (i < s.N) stage_kappa_column64(s, i, col + threadIdx.x);
+    dev_reverse_scan_e2(s, i, col + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_gather(StarDev s) {
@@ -242,7 +254,7 @@ hipError_t launch_flux(const StarDev& s, hipStream_t st) {
     if (s.scatter)
         k_flux_scatter<<<dim3((s.N + 63) / 64, 2), dim3(64, 3), 0, st>>>(s);
     else if (s.quad == PZ_QUAD_E2)
-        k_flux_e2<<<(s.N + 63) / 64, 64, 0, st>>>(s);
+        k_flux_e2<<<dim3((s.N + WAVE - 1) / WAVE, 2), WAVE, 0, st>>>(s);
     else
         k_flux<<<dim3((s.N + WAVE - 1) / WAVE, 2), WAVE, 0, st>>>(s);
     return hipGetLastError();
@@ -252,7 +264,7 @@ hipError_t launch_reverse_scan(const StarDev& s, hipStream_t st) {
     if (s.scatter)
         k_reverse_scatter<<<(s.N + 63) / 64, dim3(64, 3), 0, st>>>(s);
     else if (s.quad == PZ_QUAD_E2)
-        k_reverse_scan_e2<MAXD><<<(s.N + 63) / 64, 64, 0, st>>>(s);
+        k_reverse_scan_e2<<<(s.N + 63) / 64, 64, 0, st>>>(s);
     else
         k_reverse_scan<<<(s.N + 63) / 64, 64, 0, st>>>(s);
     return hipGetLastError();

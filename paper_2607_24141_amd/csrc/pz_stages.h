@@ -415,6 +415,24 @@ __device__ __forceinline__ double expint_n(int n, double x) {
     return h * exp(-x);
 }
 
+// E3(x) and E4(x) = (e^-x - x E3(x)) / 3 (the recurrence E_{n+1} = (e^-x -
+// x E_n) / n; its cancellation for large x costs at most ~3 of float64's 16
+// digits below x = 700, beyond which both are 0).
+__device__ __forceinline__ void expint34(double x, double& E3, double& E4) {
+    if (x <= 0.0) {
+        E3 = 0.5;
+        E4 = 1.0 / 3.0;
+        return;
+    }
+    if (x > 700.0) {
+        E3 = 0.0;
+        E4 = 0.0;
+        return;
+    }
+    E3 = expint_n(3, x);
+    E4 = (exp(-x) - x * E3) * (1.0 / 3.0);
+}
+
 // F = 2 pi int_0^inf S E2 dt for piecewise-linear S(tau): segment [ta, tb]
 // with S = Sa + s (t - ta) adds Sa (E3(ta) - E3(tb)) + s (E4(ta) - E4(tb) - (tb - ta) E3(tb));
 // below the last depth S continues linearly: S_D E3(tau_D) + s_D E4(tau_D);
@@ -427,7 +445,8 @@ struct RayE2 {
         E4a = 1.0 / 3.0;      // E4(0)
     }
     __device__ void seg(double Sa, double Sb, double ta, double tb) {
-        const double E3b = expint_n(3, tb), E4b = expint_n(4, tb);
+        double E3b, E4b;
+        expint34(tb, E3b, E4b);
         const double sl = (Sb - Sa) / (tb - ta);
         F += Sa * (E3a - E3b) + sl * (E4a - E4b - (tb - ta) * E3b);
         E3a = E3b;
@@ -439,7 +458,10 @@ struct RayE2 {
     }
 };
 
-__device__ __forceinline__ void dev_flux_e2(const StarDev& s, int i) {
+// E2 flux of pixel i on the total branch (TOT: F) and/or the continuum
+// branch (CONT: Fc), float64.
+template <bool TOT, bool CONT, class KCol>
+__device__ __forceinline__ void dev_flux_e2(const StarDev& s, int i, const KCol& kl) {
     if (i >= s.N) return;
     const double lnl = log(s.lam_first_nm) + (double)i * s.h;
     const double lam_cm = exp(lnl) * 1.0e-7;
@@ -447,38 +469,40 @@ __device__ __forceinline__ void dev_flux_e2(const StarDev& s, int i) {
     const double l2 = lam_cm * lam_cm;
     const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
     const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
-    const float* kl = s.kappa + i;
-    const size_t st = s.Npad;
     const int D = s.D;
     double S0 = c1 / expm1(c2 / s.T[0]), S1 = c1 / expm1(c2 / s.T[1]);
-    double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[st];
+    double chi0 = TOT ? kc + (double)kl[0] : 0.0, chi1 = TOT ? kc + (double)kl[1] : 0.0;
     double t0 = chi0 * s.m[0], t1 = t0 + 0.5 * (chi0 + chi1) * (s.m[1] - s.m[0]);
     double c0 = kc * s.m[0], cc1 = c0 + kc * (s.m[1] - s.m[0]);
     RayE2 rt, rc;
     rt.start();
     rc.start();
     // top slab: S_top at tau = 0 from the first segment's slope
-    rt.seg(S0 - t0 * (S1 - S0) / (t1 - t0), S0, 0.0, t0);
-    rc.seg(S0 - c0 * (S1 - S0) / (cc1 - c0), S0, 0.0, c0);
+    if (TOT) rt.seg(S0 - t0 * (S1 - S0) / (t1 - t0), S0, 0.0, t0);
+    if (CONT) rc.seg(S0 - c0 * (S1 - S0) / (cc1 - c0), S0, 0.0, c0);
     double Sa = S0, Sb = S1, ta = t0, tb = t1, ca = c0, cb = cc1, chib = chi1, mb = s.m[1];
     for (int j = 1; j < D; ++j) {
         if (j > 1) {
             const double mj = s.m[j];
-            const double chij = kc + (double)kl[(size_t)j * st];
             Sa = Sb;
-            ta = tb;
-            ca = cb;
             Sb = c1 / expm1(c2 / s.T[j]);
-            tb = ta + 0.5 * (chib + chij) * (mj - mb);
-            cb = ca + kc * (mj - mb);
-            chib = chij;
+            if (TOT) {
+                const double chij = kc + (double)kl[j];
+                ta = tb;
+                tb = ta + 0.5 * (chib + chij) * (mj - mb);
+                chib = chij;
+            }
+            if (CONT) {
+                ca = cb;
+                cb = ca + kc * (mj - mb);
+            }
             mb = mj;
         }
-        rt.seg(Sa, Sb, ta, tb);
-        rc.seg(Sa, Sb, ca, cb);
+        if (TOT) rt.seg(Sa, Sb, ta, tb);
+        if (CONT) rc.seg(Sa, Sb, ca, cb);
     }
-    s.F[i] = (float)rt.bottom(Sa, Sb, ta, tb);
-    s.Fc[i] = (float)rc.bottom(Sa, Sb, ca, cb);
+    if (TOT) s.F[i] = (float)rt.bottom(Sa, Sb, ta, tb);
+    if (CONT) s.Fc[i] = (float)rc.bottom(Sa, Sb, ca, cb);
 }
 
 // Reverse of the E2 flux for the total branch.  With knots t_{-1} = 0,
@@ -490,77 +514,72 @@ __device__ __forceinline__ void dev_flux_e2(const StarDev& s, int i) {
 //   top slab:        through E3(0) - E3(tau_0), P_0 and the extrapolated S_top;
 //   bottom:          dF/dtau_{D-1} += -s_D E3 - E4 s_D/dtau, dF/dtau_{D-2} += E4 s_D/dtau;
 // all times 2 pi; then the trapezoid suffix sums as for Gauss-3.
-template <int MD>
-__device__ __forceinline__ void dev_reverse_scan_e2(const StarDev& s, int i) {
+// col: pixel i's float64 LDS column (stride WAVE), holding kappa_line on
+// entry and dL/dtau after (each depth written once, as in dev_reverse_scan).
+__device__ __forceinline__ void dev_reverse_scan_e2(const StarDev& s, int i, double* col) {
     if (i >= s.N) return;
     const int D = s.D;
     const double G = 2.0 * PI * (double)s.dLdF[i];
-    double gt[MD];
-#pragma unroll
-    for (int j = 0; j < MD; ++j) gt[j] = 0.0;
     const double lnl = log(s.lam_first_nm) + (double)i * s.h;
     const double lam_cm = exp(lnl) * 1.0e-7;
     const double kc = s.kappa0 * exp(s.alpha * (lnl - log(s.lam_ref_nm)));
     const double l2 = lam_cm * lam_cm;
     const double c1 = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / (l2 * l2 * lam_cm) * 1.0e-7;
     const double c2 = H_PLANCK * C_LIGHT / (lam_cm * K_BOLTZ);
-    const float* kl = s.kappa + i;
-    const size_t st = s.Npad;
     const double S0 = c1 / expm1(c2 / s.T[0]), S1 = c1 / expm1(c2 / s.T[1]);
-    const double chi0 = kc + (double)kl[0], chi1 = kc + (double)kl[st];
+    const double chi0 = kc + col[0], chi1 = kc + col[WAVE];
     const double t0 = chi0 * s.m[0];
     const double t1 = t0 + 0.5 * (chi0 + chi1) * (s.m[1] - s.m[0]);
     const double d01 = t1 - t0, sig = (S1 - S0) / d01;
-    double E3a = expint_n(3, t0), E4a = expint_n(4, t0);
+    double E3a, E4a;
+    expint34(t0, E3a, E4a);
+    double g0, g1;                                     // top-slab terms of dL/dtau_0, dL/dtau_1
     {
         const double dE3 = 0.5 - E3a;                       // E3(0) - E3(tau_0)
         const double P0 = 1.0 / 3.0 - E4a - t0 * E3a;        // E4(0) - E4(tau_0) - tau_0 E3(tau_0)
-        gt[0] += G * (dE3 * (-sig - t0 * sig / d01) + P0 * sig / d01);
-        gt[1] += G * (dE3 * (t0 * sig / d01) - P0 * sig / d01);
+        g0 = G * (dE3 * (-sig - t0 * sig / d01) + P0 * sig / d01);
+        g1 = G * (dE3 * (t0 * sig / d01) - P0 * sig / d01);
     }
     double Sa = S0, Sb = S1, ta = t0, tb = t1, chib = chi1, mb = s.m[1];
-#pragma unroll
-    for (int j = 0; j < MD - 1; ++j) {
-        if (j + 1 < D) {
-            if (j > 0) {
-                const double mj = s.m[j + 1];
-                const double chij = kc + (double)kl[(size_t)(j + 1) * st];
-                Sa = Sb;
-                ta = tb;
-                Sb = c1 / expm1(c2 / s.T[j + 1]);
-                tb = ta + 0.5 * (chib + chij) * (mj - mb);
-                chib = chij;
-                mb = mj;
-            }
-            const double E3b = expint_n(3, tb), E4b = expint_n(4, tb);
-            const double dt = tb - ta, sl = (Sb - Sa) / dt;
-            const double P = E4a - E4b - dt * E3b;
-            gt[j + 1] += G * (-P * sl / dt);
-            gt[j] += G * (sl * (E3b - E3a) + P * sl / dt);
-            E3a = E3b;
-            E4a = E4b;
+    double pend = g1, last = 0.0;                      // pend: what depth j + 1 already holds
+    for (int j = 0; j < D - 1; ++j) {
+        if (j > 0) {
+            const double mj = s.m[j + 1];
+            const double chij = kc + col[(j + 1) * WAVE];
+            Sa = Sb;
+            ta = tb;
+            Sb = c1 / expm1(c2 / s.T[j + 1]);
+            tb = ta + 0.5 * (chib + chij) * (mj - mb);
+            chib = chij;
+            mb = mj;
         }
+        double E3b, E4b;
+        expint34(tb, E3b, E4b);
+        const double dt = tb - ta, sl = (Sb - Sa) / dt;
+        const double P = E4a - E4b - dt * E3b;
+        const double gj = (j == 0 ? g0 : pend) + G * (sl * (E3b - E3a) + P * sl / dt);
+        if (j < D - 2)
+            col[j * WAVE] = gj;
+        else
+            last = gj;
+        pend = (j == 0 ? g1 : 0.0) + G * (-P * sl / dt);
+        E3a = E3b;
+        E4a = E4b;
     }
     {
         const double dt = tb - ta, sD = (Sb - Sa) / dt;
-        double g_last = G * (-sD * E3a - E4a * sD / dt), g_prev = G * (E4a * sD / dt);
-#pragma unroll
-        for (int j = 0; j < MD; ++j) {
-            if (j == D - 1) gt[j] += g_last;
-            if (j == D - 2) gt[j] += g_prev;
-        }
+        col[(D - 2) * WAVE] = last + G * (E4a * sD / dt);
+        col[(D - 1) * WAVE] = pend + G * (-sD * E3a - E4a * sD / dt);
     }
     double suffix = 0.0, gnext = 0.0;
     float* out = s.gk + i;
-#pragma unroll
-    for (int j = MD - 1; j >= 0; --j) {
-        if (j < D) {
-            suffix += gt[j];
-            double g = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
-            g += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
-            out[(size_t)j * st] = (float)g;
-            gnext = suffix;
-        }
+    const size_t st = s.Npad;
+    for (int j = D - 1; j >= 0; --j) {
+        suffix += col[j * WAVE];
+        double g = (j == D - 1) ? 0.0 : 0.5 * (s.m[j + 1] - s.m[j]) * gnext;
+        g += (j == 0) ? s.m[0] * suffix : 0.5 * (s.m[j] - s.m[j - 1]) * suffix;
+        out[(size_t)j * st] = (float)g;
+        gnext = suffix;
     }
 }
 
