@@ -39,7 +39,8 @@
  *     validation happens before any device work is enqueued.
  *   - Determinism: no floating-point atomics; results are bitwise
  *     reproducible run to run, and synth_batch equals the per-star calls.
- *   - Limits: 2 <= D <= PZ_MAX_DEPTH depths, 1 <= S species, 0 <= L lines, L D < 2^31.
+ *   - Limits: 2 <= D <= PZ_MAX_DEPTH depths, 1 <= S species, 0 <= L lines, L D < 2^31,
+ *     and under 2^28 / D lines overlapping any one pixel tile (PZ_E_SHAPE).
  */
 #ifndef PZ_H
 #define PZ_H

@@ -194,6 +194,10 @@ int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species
         const int g = (int)(std::upper_bound(smin_lo.begin(), smin_lo.end(), end) - smin_lo.begin());
         tfirst[t] = f;
         tlast[t] = std::max(f, g);
+        // the opacity kernel addresses a tile's parameter rows with 32-bit byte offsets
+        if ((long long)(tlast[t] - tfirst[t]) * D >= (1LL << 28))
+            return fail(PZ_E_SHAPE, "%d lines overlap pixel tile %d: lines x n_depth per tile must be below 2^28",
+                        tlast[t] - tfirst[t], t);
     }
     // species lists over sorted lines (ascending sorted index)
     std::vector<int> sp_off(S + 1, 0), sp_idx(L);

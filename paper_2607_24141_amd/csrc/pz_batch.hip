@@ -96,7 +96,7 @@ __global__ __launch_bounds__(512) void kb_params(const StarDev* __restrict__ sta
 // G: depth-group slots (at least D / (64 / WPX) for every star).
 template <int WPX, bool ANYCT, int G>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
-    __shared__ OpacityLds<WPX, ANYCT> sm;
+    PZ_OPACITY_LDS(WPX, ANYCT, sm);
     __shared__ int s_it;
     load_pw_table(sm.pw, false);                       // visible after the first item fetch's barrier
     for (;;) {
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const St
 // Adds the lines flagged wide_a (usually none) to every (star, tile) item.
 template <int WPX, bool ANYCT>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity_wide(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n) {
-    __shared__ OpacityLds<WPX, ANYCT> sm;
+    PZ_OPACITY_LDS(WPX, ANYCT, sm);
     load_pw_table(sm.pw, false);
     __syncthreads();
     for (int it = blockIdx.x; it < n; it += gridDim.x) {

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
 // slots per lane (at least D / (64 / WPX)).
 template <int WPX, bool CT, int G>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
-    __shared__ OpacityLds<WPX, CT> sm;
+    PZ_OPACITY_LDS(WPX, CT, sm);
     __shared__ int s_it;
     load_pw_table(sm.pw, false);                       // visible after the first item fetch's barrier
     for (;;) {
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
 // Adds the lines flagged wide_a (usually none) to the tiles they overlap.
 template <int WPX, bool CT>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity_wide(StarDev s, int chunk) {
-    __shared__ OpacityLds<WPX, CT> sm;
+    PZ_OPACITY_LDS(WPX, CT, sm);
     if (s.wide_any[0] == 0) return;                   // the usual case: no flagged line
     load_pw_table(sm.pw, false);
     __syncthreads();

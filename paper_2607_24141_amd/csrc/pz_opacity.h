@@ -49,40 +49,111 @@ static constexpr float kNoLine = 2.0f;
 // LDS of one workgroup: chunk buffers of parameter rows (rows of D) and
 // detunings -- two, alternating, for the plain sum; one with the centre
 // test (CT), whose zmax rows take the room of the second and which so keeps
-// three workgroups per CU -- and the piecewise core table.
+// three workgroups per CU -- and the piecewise core table.  Each is an
+// array of its own (PZ_OPACITY_LDS declares them in the kernel): the
+// compiler then knows that reading one buffer cannot touch the copies in
+// flight into the other, and does not wait for them.
 template <int WPX, bool CT>
 struct OpacityLds {
     static constexpr int NB = CT ? 1 : 2;
-    float4 lp[NB][MAX_CHUNK * MAXD];
-    float x[NB][MAX_CHUNK * 8 * WPX];
-    float zmax[CT ? MAX_CHUNK * MAXD : 1];
-    float4 pw[PZ_PW_N * 4];
+    float4* lp0;
+    float4* lp1;
+    float* x0;
+    float* x1;
+    int* f0;                     // window fields of a chunk's lines, [NFIELD][MAX_CHUNK]
+    int* f1;
+    float* zmax;
+    float4* pw;
 };
 
-// Copies of chunk c's parameter rows (and, CT, zmax rows) into buffer b:
-// LDS element k = q D + j of the chunk is row l0 + c + q nch, depth j.  Each
+// Window fields staged per line: ilo, ihi, ic, the bits of delta, wide_a.
+static constexpr int NFIELD = 5;
+
+#define PZ_OPACITY_LDS(WPX, CT, sm)                                                        \
+    __shared__ float4 sm##_lp0[MAX_CHUNK * MAXD];                                          \
+    __shared__ float4 sm##_lp1[(CT) ? 1 : MAX_CHUNK * MAXD];                               \
+    __shared__ float sm##_x0[MAX_CHUNK * 8 * (WPX)];                                       \
+    __shared__ float sm##_x1[(CT) ? 1 : MAX_CHUNK * 8 * (WPX)];                            \
+    __shared__ int sm##_f0[(CT) ? 1 : NFIELD * MAX_CHUNK];                                 \
+    __shared__ int sm##_f1[(CT) ? 1 : NFIELD * MAX_CHUNK];                                 \
+    __shared__ float sm##_zmax[(CT) ? MAX_CHUNK * MAXD : 1];                               \
+    __shared__ float4 sm##_pw[PZ_PW_N * 4];                                                \
+    const OpacityLds<WPX, CT> sm { sm##_lp0, sm##_lp1, sm##_x0, sm##_x1, sm##_f0, sm##_f1, sm##_zmax, sm##_pw }
+
+// A wavefront-uniform pointer the compiler treats as opaque, held in scalar
+// registers: per-lane addresses are then this base plus a 32-bit offset,
+// not 64-bit induction variables kept across the chunk loop.
+__device__ __forceinline__ const char* scalar_base(const void* p) {
+    // the builtin returns int: both halves go through unsigned, so the low
+    // word is zero-extended (a sign-extended low word would corrupt the high)
+    const unsigned long long u = (unsigned long long)p;
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((unsigned)u);
+    unsigned long long v = ((unsigned long long)hi << 32) | lo;
+    asm volatile("" : "+s"(v));
+    return (const char*)v;
+}
+
+// A wavefront-uniform integer, opaque to the compiler (so nothing computed
+// from it is hoisted out of the caller's loop).
+__device__ __forceinline__ int scalar_opaque(int x) {
+    x = __builtin_amdgcn_readfirstlane(x);
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// Copies of chunk c's parameter rows (and, CT, zmax rows) into dst: LDS
+// element k = q D + j of the chunk is row l0 + c + q nch, depth j.  Each
 // wavefront instruction moves 64 elements from global memory straight into
 // consecutive LDS slots; they are complete once the issuing wavefront's load
-// counter drains.
+// counter drains.  The per-lane byte offsets fit 32 bits: the plan keeps
+// every tile's rows under 2^28 elements.
 template <int WPX, bool CT, class Lds>
-__device__ __forceinline__ void stage_rows(const StarDev& s, int l0, int c, int nch, int nc, int b, Lds& sm) {
+__device__ __forceinline__ void stage_rows(const StarDev& s, int l0, int c, int nch, int nc, float4* dst,
+                                           const Lds& sm) {
     constexpr int LPT = (MAX_CHUNK * MAXD + 511) / 512;
-    const int D = s.D, n = nc * D;
+    const size_t row0 = (size_t)(l0 + c) * s.D;
+    // offsets are recomputed per chunk, never hoisted
+    const int D = scalar_opaque(s.D), stride = scalar_opaque((nch - 1) * s.D);
+    const int n = nc * D;
     const int lane = threadIdx.x % WAVE;
+    const float inv_d = 1.0f / (float)D;
+    const char* lp = scalar_base(s.lp + row0);
+    const char* zm = CT ? scalar_base(s.zmax + row0) : nullptr;
 #pragma unroll
     for (int u = 0; u < LPT; ++u) {
         const int k0 = u * 512 + (threadIdx.x & ~(WAVE - 1));   // wavefront-uniform
         const int k = k0 + lane;
         if (k0 < n && k < n) {
-            const int q = k / D;
-            const size_t g = (size_t)(l0 + c + q * nch) * D + (k - q * D);
-            __builtin_amdgcn_global_load_lds((const void*)(s.lp + g),
-                                             (__attribute__((address_space(3))) void*)(&sm.lp[b][k0]), 16, 0, 0);
+            // k / D: (k + 1/2) / D lies at least 1/(2D) from an integer
+            const int q = (int)(((float)k + 0.5f) * inv_d);
+            const unsigned e = (unsigned)(k + q * stride);     // element offset from row0, < (l1 - l0) D
+            __builtin_amdgcn_global_load_lds((const void*)(lp + e * 16u),
+                                             (__attribute__((address_space(3))) void*)(dst + k0), 16, 0, 0);
             if (CT)
-                __builtin_amdgcn_global_load_lds((const void*)(s.zmax + g),
-                                                 (__attribute__((address_space(3))) void*)(&sm.zmax[k0]), 4, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void*)(zm + e * 4u),
+                                                 (__attribute__((address_space(3))) void*)(sm.zmax + k0), 4, 0, 0);
         }
     }
+}
+
+// Copies of the window fields of chunk c's lines into dst[NFIELD][MAX_CHUNK]
+// by wavefront 0 (lane j: line l0 + c + j nch).
+__device__ __forceinline__ void stage_fields(const StarDev& s, int l0, int c, int nch, int nc, int* dst) {
+    if (threadIdx.x >= WAVE) return;
+    const int step = scalar_opaque(nch);
+    const int j = threadIdx.x;
+    if (j >= nc) return;
+    const unsigned off = (unsigned)(j * step) * 4u;
+    auto copy = [&](const void* field, int f) {
+        __builtin_amdgcn_global_load_lds((const void*)(scalar_base((const int*)field + l0 + c) + off),
+                                         (__attribute__((address_space(3))) void*)(dst + f * MAX_CHUNK), 4, 0, 0);
+    };
+    copy(s.ln.ilo, 0);
+    copy(s.ln.ihi, 1);
+    copy(s.ln.ic, 2);
+    copy(s.ln.delta, 3);
+    copy(s.wide_a, 4);
 }
 
 // The window fields of a thread's staged (line, pixel) pairs, loaded before
@@ -90,11 +161,11 @@ __device__ __forceinline__ void stage_rows(const StarDev& s, int l0, int c, int 
 template <int WPX>
 struct XFields {
     static constexpr int XPT = (MAX_CHUNK * 8 * WPX + 511) / 512;
-    int lo[XPT], hi[XPT], ic[XPT];
+    int lo[XPT], hi[XPT], ic[XPT], wide[XPT];
     float dl[XPT];
 };
 
-template <int WPX, bool WIDE>
+template <int WPX>
 __device__ __forceinline__ void load_xfields(const StarDev& s, int l0, int c, int nch, int nc, bool any_wide,
                                              XFields<WPX>& f) {
     constexpr int TPX = 8 * WPX;
@@ -106,14 +177,34 @@ __device__ __forceinline__ void load_xfields(const StarDev& s, int l0, int c, in
         f.hi[u] = s.ln.ihi[l];
         f.ic[u] = s.ln.ic[l];
         f.dl[u] = s.ln.delta[l];
-        // a line the pass does not take gets an empty window
-        if ((any_wide && s.wide_a[l] != 0) != WIDE) f.hi[u] = f.lo[u] - 1;
+        f.wide[u] = any_wide ? s.wide_a[l] : 0;
     }
 }
 
-template <int WPX, bool CT, class Lds>
-__device__ __forceinline__ void write_x(const StarDev& s, int l0, int c, int nch, int nc, int p0, int b,
-                                        const XFields<WPX>& f, Lds& sm) {
+// A line the pass does not take (WIDE: the lines flagged wide_a; else the
+// others) gets kNoLine at every pixel.
+template <int WPX, bool WIDE>
+__device__ __forceinline__ void write_x_lds(const StarDev& s, int nc, int p0, bool any_wide, const int* fl,
+                                            float* dst) {
+    constexpr int TPX = 8 * WPX;
+#pragma unroll
+    for (int u = 0; u < XFields<WPX>::XPT; ++u) {
+        const int k = threadIdx.x + u * 512;
+        if (k < nc * TPX) {
+            const int q = k / TPX, i = p0 + (k - q * TPX);
+            const int lo = fl[q], hi = fl[MAX_CHUNK + q], ic = fl[2 * MAX_CHUNK + q];
+            const float dl = __int_as_float(fl[3 * MAX_CHUNK + q]);
+            const bool wide = any_wide && fl[4 * MAX_CHUNK + q] != 0;
+            float x = kNoLine;
+            if (wide == WIDE && i >= lo && i <= hi) x = detuning(i - ic, dl, s.h_hi, s.h_lo);
+            dst[k] = x;
+        }
+    }
+}
+
+template <int WPX, bool CT, bool WIDE>
+__device__ __forceinline__ void write_x(const StarDev& s, int l0, int c, int nch, int nc, int p0, float* dst,
+                                        const XFields<WPX>& f) {
     constexpr int TPX = 8 * WPX;
 #pragma unroll
     for (int u = 0; u < XFields<WPX>::XPT; ++u) {
@@ -121,10 +212,11 @@ __device__ __forceinline__ void write_x(const StarDev& s, int l0, int c, int nch
         if (k < nc * TPX) {
             const int q = k / TPX, i = p0 + (k - q * TPX);
             float x = kNoLine;
-            if (i >= f.lo[u] && i <= f.hi[u]) x = detuning(i - f.ic[u], f.dl[u], s.h_hi, s.h_lo);
+            if ((f.wide[u] != 0) == WIDE && i >= f.lo[u] && i <= f.hi[u])
+                x = detuning(i - f.ic[u], f.dl[u], s.h_hi, s.h_lo);
             // the slack keeps every lane the per-depth test would accept
             if (CT && !(fabsf(x) <= s.xlim[l0 + c + q * nch] * (1.0f + 1e-5f))) x = kNoLine;
-            sm.x[b][k] = x;
+            dst[k] = x;
         }
     }
 }
@@ -153,7 +245,7 @@ template <int WPX>
 constexpr int opacity_max_groups() { return MAXD / (64 / WPX); }
 
 template <int WPX, bool CT, bool WIDE, int G, class Lds>
-__device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, Lds& sm) {
+__device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, const Lds& sm) {
     constexpr int NDG = 64 / WPX;
     constexpr int DPT = G;                             // depth-group slots (>= full groups)
     static_assert(G >= 1 && G <= MAXD / NDG, "depth-group slots");
@@ -188,33 +280,28 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
     constexpr bool DB = Lds::NB == 2;                  // double-buffered chunks
     static_assert(!CT || !DB, "the centre test stages one buffer");
     XFields<WPX> f;
-    if (DB) {
-        if (nch > 0) {
-            stage_rows<WPX, CT>(s, l0, 0, nch, lines_in(0), 0, sm);
-            load_xfields<WPX, WIDE>(s, l0, 0, nch, lines_in(0), any_wide, f);
-            write_x<WPX, CT>(s, l0, 0, nch, lines_in(0), p0, 0, f, sm);
-        }
-        __builtin_amdgcn_s_waitcnt(0);                // the LDS copies count as loads
-        __syncthreads();
-    }
-    for (int c = 0; c < nch; ++c) {
-        const int b = DB ? (c & 1) : 0, nc = lines_in(c);
+    // Sums chunk c from (rows, xs).  DB: first starts the copies of chunk
+    // c + 1's rows into nrows and of chunk c + 2's window fields into fcur;
+    // after the sum, chunk c + 1's detunings go to nxs from fnext (its
+    // fields, copied during chunk c - 1).
+    auto chunk_pass = [&](int c, const float4* rows, const float* xs, float4* nrows, float* nxs, int* fcur,
+                          const int* fnext) __attribute__((always_inline)) {
+        const int nc = lines_in(c);
         const bool more = DB && c + 1 < nch;
         if (!DB) {                                     // one buffer: stage, then sum
-            stage_rows<WPX, CT>(s, l0, c, nch, nc, 0, sm);
-            load_xfields<WPX, WIDE>(s, l0, c, nch, nc, any_wide, f);
-            write_x<WPX, CT>(s, l0, c, nch, nc, p0, 0, f, sm);
+            stage_rows<WPX, CT>(s, l0, c, nch, nc, sm.lp0, sm);
+            load_xfields<WPX>(s, l0, c, nch, nc, any_wide, f);
+            write_x<WPX, CT, WIDE>(s, l0, c, nch, nc, p0, sm.x0, f);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-        } else if (more) {                             // chunk c + 1 into the other buffer
-            stage_rows<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), b ^ 1, sm);
-            load_xfields<WPX, WIDE>(s, l0, c + 1, nch, lines_in(c + 1), any_wide, f);
+        } else {
+            if (more) stage_rows<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), nrows, sm);
+            if (c + 2 < nch) stage_fields(s, l0, c + 2, nch, lines_in(c + 2), fcur);
         }
-        const float4* rows = sm.lp[b];
         for (int q = 0; q < nc; ++q) {
             const float4* row = rows + q * D;
             const float* zrow = CT ? &sm.zmax[q * D] : nullptr;
-            const float x = sm.x[b][q * TPX + px];
+            const float x = xs[q * TPX + px];
             if (x < 1.0f) {
                 float4 pd[DPT];
                 float z2[DPT];
@@ -249,16 +336,34 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
                 }
             }
             if (tail) {
-                const float xt = sm.x[b][q * TPX + tpx];
+                const float xt = xs[q * TPX + tpx];
                 if (xt < 1.0f) {
                     const float4 p = row[tj];
                     acc_t = voigt_acc<CT, WIDE>(acc_t, p.y, p.z, p.w, xt * p.x, sm.pw, CT ? zrow[tj] : 0.0f);
                 }
             }
         }
-        if (more) write_x<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), p0, b ^ 1, f, sm);
+        if (more) write_x_lds<WPX, WIDE>(s, lines_in(c + 1), p0, any_wide, fnext, nxs);
         if (DB) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+    };
+    if (DB) {
+        // The buffers alternate with a static role in each half of the
+        // unrolled pair, so every LDS access names its own array.
+        if (nch > 0) {
+            stage_rows<WPX, CT>(s, l0, 0, nch, lines_in(0), sm.lp0, sm);
+            if (nch > 1) stage_fields(s, l0, 1, nch, lines_in(1), sm.f1);
+            load_xfields<WPX>(s, l0, 0, nch, lines_in(0), any_wide, f);
+            write_x<WPX, CT, WIDE>(s, l0, 0, nch, lines_in(0), p0, sm.x0, f);
+        }
+        __builtin_amdgcn_s_waitcnt(0);                // the LDS copies count as loads
+        __syncthreads();
+        for (int c = 0; c < nch; c += 2) {
+            chunk_pass(c, sm.lp0, sm.x0, sm.lp1, sm.x1, sm.f0, sm.f1);
+            if (c + 1 < nch) chunk_pass(c + 1, sm.lp1, sm.x1, sm.lp0, sm.x0, sm.f1, sm.f0);
+        }
+    } else {
+        for (int c = 0; c < nch; ++c) chunk_pass(c, sm.lp0, sm.x0, nullptr, nullptr, nullptr, nullptr);
     }
     const int i = p0 + px;
     if (i < s.N) {
@@ -284,7 +389,7 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 // stars with the centre test are taken too.
 // G: depth-group slots, at least the star's D / NDG.
 template <int WPX, bool WIDE, bool ANYCT, int G>
-__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, OpacityLds<WPX, ANYCT>& sm) {
+__device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, const OpacityLds<WPX, ANYCT>& sm) {
     if (ANYCT && s.center)
         opacity_tile_body<WPX, ANYCT, WIDE, G>(s, tile, chunk, sm);
     else

@@ -62,7 +62,7 @@ def _create(pz, grid=None, lines=None, S=2, D=8, opts=None):
 @pytest.mark.parametrize("case,code", [
     ("N", -2), ("R", -1), ("lam", -1), ("D", -2), ("Dbig", -2), ("S", -2), ("W", -1), ("quad", -1),
     ("tile", -1), ("flags", -1), ("species", -1), ("ion", -1), ("nan", -5), ("eta", -1), ("eta_nan", -1),
-    ("scat_iter", -1), ("scat_tol", -1), ("scat_e2", -6), ("LD", -2)])
+    ("scat_iter", -1), ("scat_tol", -1), ("scat_e2", -6), ("LD", -2), ("tileLD", -2)])
 def test_plan_validation(pz, case, code):
     import numpy as np
     kw = {}
@@ -106,6 +106,10 @@ def test_plan_validation(pz, case, code):
         ln, keep = _lines(pz)
         ln.L = 27_000_000
         kw["lines"] = (ln, keep)
+        kw["D"] = pz.PZ_MAX_DEPTH
+    elif case == "tileLD":                   # 3.4e6 lines over one pixel tile: 2.7e8 rows >= 2^28
+        L = 3_400_000
+        kw["lines"] = _lines(pz, L, lam0=np.full(L, 500.1))
         kw["D"] = pz.PZ_MAX_DEPTH
     rc, msg = _create(pz, **kw)
     assert rc == code, (rc, msg)
