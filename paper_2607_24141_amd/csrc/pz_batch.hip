@@ -104,7 +104,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const St
         if (it >= n) return;
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, false, ANYCT, G>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, false, ANYCT, G, false>(s, w.y, s.chunk, sm);
     }
 }
 
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity_wide(con
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, true, ANYCT, opacity_max_groups<WPX>()>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, true, ANYCT, opacity_max_groups<WPX>(), false>(s, w.y, s.chunk, sm);
     }
 }
 

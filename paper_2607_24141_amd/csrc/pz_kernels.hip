@@ -40,7 +40,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
         const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= s.n_tiles) return;
-        dev_opacity_tile<WPX, false, CT, G>(s, s.tile_order[it], chunk, sm);
+        dev_opacity_tile<WPX, false, CT, G, true>(s, s.tile_order[it], chunk, sm);
     }
 }
 
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity_wide(Star
     load_pw_table(sm.pw, false);
     __syncthreads();
     for (int t = blockIdx.x; t < s.n_tiles; t += gridDim.x)
-        dev_opacity_tile<WPX, true, CT, opacity_max_groups<WPX>()>(s, t, chunk, sm);
+        dev_opacity_tile<WPX, true, CT, opacity_max_groups<WPX>(), true>(s, t, chunk, sm);
 }
 
 __global__ void k_reset_queue(int* ctr) { ctr[0] = 0; }

@@ -244,7 +244,7 @@ __device__ __forceinline__ void wing_sums(float* acc, const float4* pd, const fl
 template <int WPX>
 constexpr int opacity_max_groups() { return MAXD / (64 / WPX); }
 
-template <int WPX, bool CT, bool WIDE, int G, class Lds>
+template <int WPX, bool CT, bool WIDE, int G, bool PAIRED, class Lds>
 __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, const Lds& sm) {
     constexpr int NDG = 64 / WPX;
     constexpr int DPT = G;                             // depth-group slots (>= full groups)
@@ -281,9 +281,10 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
     static_assert(!CT || !DB, "the centre test stages one buffer");
     XFields<WPX> f;
     // Sums chunk c from (rows, xs).  DB: first starts the copies of chunk
-    // c + 1's rows into nrows and of chunk c + 2's window fields into fcur;
-    // after the sum, chunk c + 1's detunings go to nxs from fnext (its
-    // fields, copied during chunk c - 1).
+    // c + 1's rows into nrows; PAIRED, also of chunk c + 2's window fields
+    // into fcur, and after the sum chunk c + 1's detunings go to nxs from
+    // fnext (its fields, copied during chunk c - 1); else chunk c + 1's
+    // fields are loaded into registers first and its detunings written after.
     auto chunk_pass = [&](int c, const float4* rows, const float* xs, float4* nrows, float* nxs, int* fcur,
                           const int* fnext) __attribute__((always_inline)) {
         const int nc = lines_in(c);
@@ -294,9 +295,12 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
             write_x<WPX, CT, WIDE>(s, l0, c, nch, nc, p0, sm.x0, f);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-        } else {
+        } else if (PAIRED) {
             if (more) stage_rows<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), nrows, sm);
             if (c + 2 < nch) stage_fields(s, l0, c + 2, nch, lines_in(c + 2), fcur);
+        } else if (more) {
+            stage_rows<WPX, CT>(s, l0, c + 1, nch, lines_in(c + 1), nrows, sm);
+            load_xfields<WPX>(s, l0, c + 1, nch, lines_in(c + 1), any_wide, f);
         }
         for (int q = 0; q < nc; ++q) {
             const float4* row = rows + q * D;
@@ -343,24 +347,39 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
                 }
             }
         }
-        if (more) write_x_lds<WPX, WIDE>(s, lines_in(c + 1), p0, any_wide, fnext, nxs);
+        if (more) {
+            if (PAIRED)
+                write_x_lds<WPX, WIDE>(s, lines_in(c + 1), p0, any_wide, fnext, nxs);
+            else
+                write_x<WPX, CT, WIDE>(s, l0, c + 1, nch, lines_in(c + 1), p0, nxs, f);
+        }
         if (DB) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     };
     if (DB) {
-        // The buffers alternate with a static role in each half of the
-        // unrolled pair, so every LDS access names its own array.
         if (nch > 0) {
             stage_rows<WPX, CT>(s, l0, 0, nch, lines_in(0), sm.lp0, sm);
-            if (nch > 1) stage_fields(s, l0, 1, nch, lines_in(1), sm.f1);
+            if (PAIRED && nch > 1) stage_fields(s, l0, 1, nch, lines_in(1), sm.f1);
             load_xfields<WPX>(s, l0, 0, nch, lines_in(0), any_wide, f);
             write_x<WPX, CT, WIDE>(s, l0, 0, nch, lines_in(0), p0, sm.x0, f);
         }
         __builtin_amdgcn_s_waitcnt(0);                // the LDS copies count as loads
         __syncthreads();
-        for (int c = 0; c < nch; c += 2) {
-            chunk_pass(c, sm.lp0, sm.x0, sm.lp1, sm.x1, sm.f0, sm.f1);
-            if (c + 1 < nch) chunk_pass(c + 1, sm.lp1, sm.x1, sm.lp0, sm.x0, sm.f1, sm.f0);
+        if (PAIRED) {
+            // The buffers alternate with a static role in each half of the
+            // unrolled pair, so every LDS access names its own array.
+            for (int c = 0; c < nch; c += 2) {
+                chunk_pass(c, sm.lp0, sm.x0, sm.lp1, sm.x1, sm.f0, sm.f1);
+                if (c + 1 < nch) chunk_pass(c + 1, sm.lp1, sm.x1, sm.lp0, sm.x0, sm.f1, sm.f0);
+            }
+        } else {
+            // One loop body, the buffer chosen at run time (fewer registers;
+            // the loads of a chunk then wait for the copies in flight).
+            for (int c = 0; c < nch; ++c) {
+                const bool odd = c & 1;
+                chunk_pass(c, odd ? sm.lp1 : sm.lp0, odd ? sm.x1 : sm.x0, odd ? sm.lp0 : sm.lp1,
+                           odd ? sm.x0 : sm.x1, nullptr, nullptr);
+            }
         }
     } else {
         for (int c = 0; c < nch; ++c) chunk_pass(c, sm.lp0, sm.x0, nullptr, nullptr, nullptr, nullptr);
@@ -387,13 +406,16 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 // far wing tiers across depths) with the evaluator that keeps each lane on
 // its own tier.  ANYCT: the workgroup's LDS has the centre test's rows, so
 // stars with the centre test are taken too.
-// G: depth-group slots, at least the star's D / NDG.
-template <int WPX, bool WIDE, bool ANYCT, int G>
+// G: depth-group slots, at least the star's D / NDG.  PAIRED: the plain sum
+// runs its chunks in statically paired buffers (faster where the registers
+// allow, as in the single-star kernels; the batch kernels, which also hold
+// their work queue's state, take the one-body loop).
+template <int WPX, bool WIDE, bool ANYCT, int G, bool PAIRED>
 __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, const OpacityLds<WPX, ANYCT>& sm) {
     if (ANYCT && s.center)
-        opacity_tile_body<WPX, ANYCT, WIDE, G>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, ANYCT, WIDE, G, PAIRED>(s, tile, chunk, sm);
     else
-        opacity_tile_body<WPX, false, WIDE, G>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, false, WIDE, G, PAIRED>(s, tile, chunk, sm);
 }
 
 }  // namespace pz
