@@ -90,6 +90,34 @@ def test_batch_bitwise_equals_per_star(gpu_lib, mode):
     batch.destroy()
 
 
+@pytest.mark.parametrize("chunk", [1, 3, 5])
+def test_batch_small_lds_chunks_bitwise(gpu_lib, chunk):
+    """The batch kernels' chunk loop (one body, the LDS buffer chosen at run
+    time) against the single-star kernels' paired loop, with chunks of 1 to 5
+    lines (tiles of 4 to 59 lines: chunk counts from 1 to 59): the same sums
+    in the same order, so bitwise equal outputs."""
+    pz = gpu_lib
+    stars = []
+    for k, (L, D, tile) in enumerate([(61, 72, 32), (20, 72, 64), (9, 40, 32)]):
+        wl = W.tiny(seed=76 + k, L=L, N=400, D=D, S=4, n_molecular=1)
+        wl.params = W.random_params(np.random.default_rng(76 + k), L, 4, 1.2)
+        st = Star(pz, wl, tile, target=(k == 0), seed=k)
+        st.plan = pz.plan_for(wl, tile_px=tile, lines_per_chunk=chunk)
+        stars.append(st)
+    batch = pz.Batch([s.descr(pz) for s in stars])
+    print("synth_batch chunk", chunk, flush=True)
+    pz.synth_batch(batch, pz.PZ_MODE_FWD_BWD)
+    torch.cuda.synchronize()
+    got = [s.outputs() for s in stars]
+    for s in stars:
+        s.sequential(pz, pz.PZ_MODE_FWD_BWD)
+    torch.cuda.synchronize()
+    for k, s in enumerate(stars):
+        for a, b in zip(got[k], s.outputs()):
+            np.testing.assert_array_equal(a, b)
+    batch.destroy()
+
+
 def test_batch_graph_replay(gpu_lib):
     """The whole forward+backward batch captured in one graph; every replay
     (with eager work and synchronisations in between) equals the eager run."""

@@ -5,8 +5,9 @@ one line), the largest depth count (D = 80), strongly damped lines (a from
 the perturber density between adjacent layers (a from ~1 to ~3e4 inside one
 wavefront), damping ratios from ~3 to ~900 over the depths of every line (one
 wing tier for all of a wavefront's depth groups), 200 identical lines in one
-tile (many LDS chunks), and the backward of an empty catalogue (zero
-abundance and microturbulence gradients)."""
+tile (many LDS chunks), every LDS chunk count of a tile from 1 to 59, and
+the backward of an empty catalogue (zero abundance and microturbulence
+gradients)."""
 import copy
 
 import numpy as np
@@ -129,6 +130,40 @@ def test_identical_lines_pile_up(gpu_lib):
     assert np.max(np.abs(got - ref) / (ref + 1e-6 * kc)) <= 2e-5
     single = W.Workload("single", wl.grid, wl.atm, wl.lines.take([0]), W.zero_params(1, 3, 1.0))
     np.testing.assert_allclose(got, 200.0 * _kappa(gpu_lib, single), rtol=2e-5, atol=1e-30)
+
+
+def _kappa_opts(pz, wl, **kw):
+    plan = pz.plan_for(wl, **kw)
+    kap = torch.empty((wl.atm.D, wl.grid.N), dtype=torch.float32, device="cuda")
+    print("pz_line_opacity", wl.name, kw, flush=True)
+    pz.pz_line_opacity(plan, pz.Atmos(wl.atm), pz.Params.from_host(wl.params), kap)
+    torch.cuda.synchronize()
+    return kap.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("L,chunk", [(61, 1), (61, 2), (61, 3), (61, 5), (20, 7), (20, 16), (9, 16), (9, 3)])
+def test_lds_chunk_counts(gpu_lib, L, chunk):
+    """The tiles of these cases hold 4 to 59 lines, so LDS chunks of 1 to 16
+    lines give every chunk count from 1 to 59, odd and even: the paired
+    double buffer (first and second of a pair, the last chunk alone, the
+    window fields staged two chunks ahead) and the centre test's single
+    buffer.  Plain opacity against the oracle at two tile widths; with the
+    centre test, the same opacity as with 16-line chunks up to the rounding
+    of a different line order."""
+    pz = gpu_lib
+    wl = W.tiny(seed=76, L=L, N=400, D=72, S=4, n_molecular=1)
+    wl.params = W.random_params(np.random.default_rng(76), L, 4, 1.2)
+    ref = O.line_opacity(wl, wl.params)
+    kc = O.continuum_opacity(wl)[None, :]
+    for tile in (32, 64):
+        got = _kappa_opts(pz, wl, tile_px=tile, lines_per_chunk=chunk)
+        err = np.abs(got - ref) / (ref + 1e-6 * kc)
+        print("L %d chunk %d tile %d: max kappa err %.3e" % (L, chunk, tile, err.max()), flush=True)
+        assert err.max() <= 2e-5
+    wl.center_eta = 1e-3
+    a = _kappa_opts(pz, wl, lines_per_chunk=chunk)
+    b = _kappa_opts(pz, wl, lines_per_chunk=16)
+    assert np.all(np.abs(a - b) <= 2e-6 * np.abs(b) + 1e-9 * kc)
 
 
 def test_backward_of_empty_catalogue(gpu_lib):
