@@ -231,8 +231,10 @@ __device__ __forceinline__ float voigt_acc(float acc, float a2, float K, float K
         core_w(sqrt((double)a2), (double)v, wr, wi);
         return (float)fma((double)K, wr, (double)acc);
     }
-    if (z2 < PZ_VOIGT_TIER2_R2) return fmaf(Ka, wing_S<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W), acc);
-    if (SAFE && z2 >= PZ_VOIGT_TIER3_R2) return fmaf(Ka, wing_S<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W), acc);
+    // The wing lanes beside core lanes: without SAFE all take the six-node
+    // sum (one pass instead of two; in range, as for the uniform case above).
+    if (!SAFE || z2 < PZ_VOIGT_TIER2_R2) return fmaf(Ka, wing_S<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W), acc);
+    if (z2 >= PZ_VOIGT_TIER3_R2) return fmaf(Ka, wing_S<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W), acc);
     return fmaf(Ka, wing_S<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W), acc);
 }
 
