@@ -62,3 +62,43 @@ def test_target_and_seed_reproduce(golden):
     dF, _ = O.chi2_seed(F, Fc, z["y"][pix].astype(np.float64), wl.extra["sigma"])
     scale = np.max(np.abs(z["seed"]))
     assert np.max(np.abs(z["seed"][pix] - dF)) <= 1e-5 * scale
+
+
+# ------------------------------------------------ full-pixel flux goldens
+# tests/golden/flux_1500_1700nm_golden.npz and flux_300_1000nm_slices_golden.npz
+# (written by tests/golden/make_flux_goldens.py from the oracle alone).  The
+# stored values are what the oracle gives on re-evaluation at sampled pixels,
+# and the slices are the 2-nm pieces they claim to be.
+FLUX_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "flux_1500_1700nm_golden.npz")
+SLICE_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "flux_300_1000nm_slices_golden.npz")
+
+
+def test_flux_golden_1500_1700nm_reproduces():
+    z = np.load(FLUX_GOLDEN)
+    wl = W.giant_1500_1700nm()
+    assert z["F"].shape == (wl.grid.N,) and str(z["workload"]) == wl.name
+    rng = np.random.default_rng(6)
+    pix = np.unique(np.concatenate([[0, wl.grid.N - 1], rng.integers(0, wl.grid.N, 10)]))
+    F, Fc = O.synthesize(wl, pix=pix)
+    np.testing.assert_allclose(z["F"][pix], F, rtol=1e-12)
+    np.testing.assert_allclose(z["Fc"][pix], Fc, rtol=1e-12)
+    assert np.all(z["F"] > 0) and np.all(z["F"] <= z["Fc"])
+
+
+def test_flux_golden_300_1000nm_slices():
+    z = np.load(SLICE_GOLDEN)
+    wl = W.solar_300_1000nm()
+    lam = O.wavelengths_nm(wl.grid)
+    pix = z["pix"]
+    starts = np.flatnonzero(np.diff(pix) != 1) + 1
+    pieces = np.split(pix, starts)
+    assert len(pieces) == 3
+    assert pieces[0][0] == 0 and pieces[2][-1] == wl.grid.N - 1
+    assert abs(lam[pieces[1][0]] - 650.0) < 0.01
+    for p in pieces:                               # each slice spans 2 nm
+        assert 1.99 < lam[p[-1]] - lam[p[0]] < 2.0
+    rng = np.random.default_rng(7)
+    sel = np.unique(np.concatenate([[0, pix.size - 1], rng.integers(0, pix.size, 4)]))
+    F, Fc = O.synthesize(wl, pix=pix[sel])
+    np.testing.assert_allclose(z["F"][sel], F, rtol=1e-12)
+    np.testing.assert_allclose(z["Fc"][sel], Fc, rtol=1e-12)

@@ -1,14 +1,17 @@
 """GPU vector-Jacobian product (Sec. 6, Eq. 30 corrections) against the FP64
 oracle adjoint with the identical seed, through the C ABI.
 
-Gradient tolerance.  A gradient is a sum over (pixel, depth) terms
-t = dL/dkappa dkappa/dp that can cancel heavily (random-sign seeds, or the
-noise-dominated residuals of a chi^2 fit).  Each float32 term carries a
-relative error of order 1e-6 (Voigt evaluation <= 1.5e-6, float32 rounding of
-the per-(line, depth) parameters and of dL/dkappa), so the achievable error
-is |g - g_ref| <= 1e-3 |g_ref| + 1e-5 sum|t|: 1e-3 relative for every
-gradient whose terms cancel by less than a factor 100, and an error bounded by
-the term accuracy otherwise.  sum|t| comes from the oracle (conditions=True).
+Gradient tolerance.  The rule is 1e-3 relative where |g_ref| >= 1e-2 of the
+largest |g_ref| of its kind, and 1e-5 of that largest value below it (a
+near-zero gradient is a difference of rounding-level terms).  A gradient is a
+sum over (pixel, depth) terms t = dL/dkappa dkappa/dp; with random-sign seeds
+the terms of a few gradients cancel by more than a factor 100 (sum|t| >
+100 |g_ref|).  Each float32 term carries a relative error of order 1e-6
+(Voigt evaluation <= 1.5e-6, float32 rounding of the per-(line, depth)
+parameters and of dL/dkappa), so for those entries alone, and only on the
+small random cases, the bound is 1e-3 |g_ref| + 1e-5 sum|t| (sum|t| from the
+oracle, conditions=True); their number is printed.  The full-size gradients
+(the chi^2 seed of the differentiation workload) are held to the plain rule.
 """
 import numpy as np
 import pytest
@@ -21,17 +24,44 @@ pytestmark = pytest.mark.gpu
 
 
 TERM_TOL = 1e-5
+COND_LIMIT = 100.0
+
+
+def s17_ok(got, ref, rtol=1e-3, floor=1e-5):
+    """Elementwise: 1e-3 relative where |ref| >= 1e-2 max|ref|, else 1e-5 max|ref|."""
+    got, ref = (np.atleast_1d(np.asarray(x, np.float64)) for x in (got, ref))
+    scale = np.max(np.abs(ref)) if ref.size else 0.0
+    err = np.abs(got - ref)
+    big = np.abs(ref) >= 1e-2 * scale
+    return np.where(big, err <= rtol * np.abs(ref), err <= floor * scale)
+
+
+def grad_close_s17(got, ref, rtol=1e-3, name=""):
+    """Assert the plain rule on every entry; returns the worst relative error among the large ones."""
+    got, ref = (np.atleast_1d(np.asarray(x, np.float64)) for x in (got, ref))
+    ok = s17_ok(got, ref, rtol)
+    bad = np.flatnonzero(~ok)
+    assert bad.size == 0, (name, bad[:5], got[bad[:5]], ref[bad[:5]])
+    scale = np.max(np.abs(ref))
+    big = np.abs(ref) >= 1e-2 * scale
+    return float(np.max(np.abs(got - ref)[big] / np.abs(ref[big]), initial=0.0))
 
 
 def grad_close_cond(got, ref, abs_sum, rtol=1e-3, name=""):
-    """|g - g_ref| <= rtol |g_ref| + TERM_TOL sum|t|; returns the share within rtol alone."""
+    """The plain rule, except for entries whose terms cancel by more than COND_LIMIT
+    (sum|t| > COND_LIMIT |g_ref|): those may instead meet rtol |g_ref| + TERM_TOL sum|t|.
+    Returns the number of entries that needed the conditioning bound."""
     got, ref, a = (np.atleast_1d(np.asarray(x, np.float64)) for x in (got, ref, abs_sum))
     err = np.abs(got - ref)
-    bound = rtol * np.abs(ref) + TERM_TOL * a
-    bad = np.flatnonzero(err > bound)
+    ok = s17_ok(got, ref, rtol)
+    illcond = a > COND_LIMIT * np.abs(ref)
+    ok_cond = illcond & (err <= rtol * np.abs(ref) + TERM_TOL * a)
+    bad = np.flatnonzero(~(ok | ok_cond))
     assert bad.size == 0, (name, bad[:5], got[bad[:5]], ref[bad[:5]], a[bad[:5]])
-    nz = np.abs(ref) > 0
-    return float(np.mean(err[nz] <= rtol * np.abs(ref[nz]))) if nz.any() else 1.0
+    n_cond = int(np.sum(~ok & ok_cond))
+    print("%s: %d of %d entries within the conditioning bound only (%d ill-conditioned)"
+          % (name, n_cond, got.size, int(illcond.sum())))
+    return n_cond
 
 
 def grad_close(got, ref, rtol=1e-3, name=""):

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import workloads as W
-from test_gpu_adjoint import grad_close_cond
+from test_gpu_adjoint import grad_close_s17
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fit_1500_1700nm_golden.npz")
@@ -54,18 +54,36 @@ def test_loss_and_seed(run):
     assert np.max(np.abs(run["gF"] - seed)) <= 2e-3 * np.max(np.abs(seed))
 
 
+def _conditioning(got, ref, abs_sum, name):
+    big = np.abs(ref) >= 1e-2 * np.max(np.abs(ref))
+    cond = abs_sum[big] / np.abs(ref[big])
+    err = np.abs(got - ref)[big] / np.abs(ref[big])
+    print("%s: %d large of %d, max sum|t|/|g| %.1f, worst rel err %.2e, share within 1e-3 %.3f"
+          % (name, int(big.sum()), ref.size, cond.max(initial=0), err.max(initial=0),
+             float(np.mean(np.abs(got - ref)[np.abs(ref) > 0] <= 1e-3 * np.abs(ref[np.abs(ref) > 0])))))
+
+
 def test_line_gradients(run):
+    """288 sampled lines (256 random, the 32 largest |dL/d loggf|): dL/d loggf and
+    dL/d ddamp within 1e-3 relative where |g_ref| >= 1e-2 of the largest of its
+    kind, and within 1e-5 of the largest below that."""
     z = run["z"]
     lines = z["lines"]
-    share_gf = grad_close_cond(run["g"][0][lines], z["g_loggf"], z["abs_loggf"], name="loggf")
-    share_d = grad_close_cond(run["g"][1][lines], z["g_damp"], z["abs_damp"], name="damp")
-    print("share within 1e-3 rel: loggf %.3f damp %.3f" % (share_gf, share_d))
+    for k, name in ((0, "loggf"), (1, "damp")):
+        got, ref = run["g"][k][lines], z["g_" + name]
+        _conditioning(got, ref, z["abs_" + name], name)
+        grad_close_s17(got, ref, name=name)
 
 
 def test_species_and_xi_gradients(run):
+    """The 20 abundance gradients (same rule) and the microturbulence gradient
+    (1e-3 relative)."""
     z = run["z"]
-    grad_close_cond(run["g"][2], z["g_abund"], z["abs_abund"], name="abund")
-    grad_close_cond(run["g"][3], np.atleast_1d(z["g_xi"]), np.atleast_1d(z["abs_xi"]), name="xi")
+    _conditioning(run["g"][2], z["g_abund"], z["abs_abund"], "abund")
+    grad_close_s17(run["g"][2], z["g_abund"], name="abund")
+    g_xi, ref_xi = run["g"][3][0], float(z["g_xi"])
+    print("xi: got %.6e ref %.6e sum|t|/|g| %.1f" % (g_xi, ref_xi, float(z["abs_xi"]) / abs(ref_xi)))
+    assert abs(g_xi - ref_xi) <= 1e-3 * abs(ref_xi), (g_xi, ref_xi)
 
 
 def test_fd_parameters(run):

@@ -8,6 +8,7 @@ import pytest
 import scipy.constants as sc
 from scipy import integrate
 from numpy.polynomial.legendre import leggauss
+from scipy.special import expn
 
 import workloads as W
 from oracle import synth as O
@@ -164,6 +165,86 @@ def test_e2_equals_angle_integral():
     # Gauss-3 is a different (coarser) angular rule: close but not identical
     g3 = O.flux_gauss3(S, tau)
     assert 1e-7 < abs(g3[0] / F[0] - 1) < 1e-2
+
+
+# Shallow atmospheres: at tau_max of order one the lower boundary carries a
+# large share of the flux (the diffusion intensity I = S + mu dS/dtau behind
+# the last layer for Gauss-3, the tail S_D E3(tau_D) + s_D E4(tau_D) of the E2
+# form), so every closed form below also pins those terms (Eqs. 7-8).
+SHALLOW = (0.3, 2.0)
+
+
+def _shallow_tau(tau_max, cols=1):
+    return np.geomspace(1e-4 * tau_max, tau_max, 72)[:, None] * np.linspace(1.0, 0.5, cols)[None, :]
+
+
+@pytest.mark.parametrize("quad", ["gauss3", "e2"])
+@pytest.mark.parametrize("tau_max", SHALLOW)
+def test_linear_source_flux_shallow(quad, tau_max):
+    """S = a + b tau through a slab of depth tau_max ~ 1: still F = pi (a + 2b/3) exactly.
+
+    The semi-infinite linear atmosphere gives I(0, mu) = a + b mu; the diffusion
+    boundary continues S linearly below the last layer, so any depth of slab
+    reproduces it.  The boundary term is checked to carry a large share of the
+    flux, so a dropped or mis-signed term (or a missing mu) fails the test."""
+    tau = _shallow_tau(tau_max, 3)
+    a, b = 2.0, 3.0
+    S = a + b * tau
+    F = O.emergent_flux(S, tau, quad)
+    np.testing.assert_allclose(F, math.pi * (a + 2 * b / 3), rtol=1e-12)
+    tD = tau[-1]
+    bottom = 2 * math.pi * (S[-1] * expn(3, tD) + b * expn(4, tD))
+    assert np.all(bottom / F > 0.05), bottom / F
+
+
+@pytest.mark.parametrize("tau_max", SHALLOW)
+def test_milne_eddington_ratio_shallow(tau_max):
+    """The Milne-Eddington ratio with the continuum slab only tau_max deep."""
+    tc = _shallow_tau(tau_max) * np.ones((1, 4))
+    eta = np.array([0.0, 0.3, 5.0, 300.0])[None, :]
+    a, b = 1.0, 2.5
+    S = a + b * tc
+    for quad in ("gauss3", "e2"):
+        ratio = O.emergent_flux(S, tc * (1 + eta), quad) / O.emergent_flux(S, tc, quad)
+        expect = (a + 2 * b / (3 * (1 + eta[0]))) / (a + 2 * b / 3)
+        np.testing.assert_allclose(ratio, expect, rtol=1e-11)
+
+
+@pytest.mark.parametrize("tau_max", SHALLOW)
+def test_e2_equals_angle_integral_shallow(tau_max):
+    """A curved source in a shallow slab: the E2 form (with its E3/E4 tail) equals
+    the 64-angle integral of I(0, mu), whose rays start from the diffusion
+    intensity S_D + mu s_D at the bottom."""
+    tau = _shallow_tau(tau_max, 2)
+    S = np.exp(-1.0 / (0.3 + tau)) + 0.2 * np.sqrt(tau) + 0.7 * tau ** 2
+    x, w = leggauss(64)
+    mu, w = 0.5 * (x + 1), 0.5 * w
+    F = sum(2 * math.pi * wk * mk * O.intensity_surface(S, tau, mk) for mk, wk in zip(mu, w))
+    np.testing.assert_allclose(O.flux_e2(S, tau), F, rtol=1e-9)
+
+
+@pytest.mark.parametrize("tau_max", SHALLOW)
+@pytest.mark.parametrize("mu", [0.05, 0.1127016653792583, 0.5, 0.8872983346207417, 1.0])
+def test_intensity_is_the_formal_integral_shallow(tau_max, mu):
+    """I(0, mu) from the layer recursion equals the formal solution of Eq. 7
+    written as one integral, I = int_0^tau_D S(t) e^{-t/mu} dt/mu +
+    (S_D + mu s_D) e^{-tau_D/mu}, with S piecewise linear in tau (extended
+    linearly to tau = 0), integrated by adaptive quadrature segment by segment."""
+    tau = _shallow_tau(tau_max)[:, 0]
+    S = 1.0 + np.sin(3.0 * tau / tau_max) + 0.4 * (tau / tau_max) ** 2
+    knots_t = np.concatenate([[0.0], tau])
+    S0 = S[0] - tau[0] * (S[1] - S[0]) / (tau[1] - tau[0])
+    knots_S = np.concatenate([[S0], S])
+    total = 0.0
+    for k in range(len(knots_t) - 1):
+        ta, tb, Sa, Sb = knots_t[k], knots_t[k + 1], knots_S[k], knots_S[k + 1]
+        f = lambda t: (Sa + (Sb - Sa) * (t - ta) / (tb - ta)) * math.exp(-t / mu) / mu
+        val, _ = integrate.quad(f, ta, tb, epsabs=0, epsrel=1e-13)
+        total += val
+    sD = (S[-1] - S[-2]) / (tau[-1] - tau[-2])
+    total += (S[-1] + mu * sD) * math.exp(-tau[-1] / mu)
+    got = float(O.intensity_surface(S[:, None], tau[:, None], mu)[0])
+    assert abs(got / total - 1) < 1e-12, (got, total)
 
 
 def test_lin_weight_series_matches_direct():
