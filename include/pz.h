@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define PZ_VERSION 4
+#define PZ_VERSION 5
 #define PZ_MAX_DEPTH 80
 
 #define PZ_OK 0
@@ -203,6 +203,28 @@ int synth_backward(const pz_plan* plan, const pz_atmos* atm, const pz_params* pa
                    const float* dL_dF, const float* dL_dFc,
                    float* g_loggf, float* g_damp, float* g_abund, float* g_xi,
                    pz_stream stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward synthesis as synth_forward, same kernels and bitwise the same F and
+ * Fc, with its per-call workspace (populations, line factors, the
+ * per-(line, depth) parameters, the line opacity kappa_line[D][Npad], the
+ * opacity work-queue counter and the centre-test masks) in one static device
+ * array of PZ_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until the
+ * process ends.  No allocation, no memset, no host synchronisation.
+ *   - The plan must have been created on the current device.
+ *   - Fails with PZ_E_SHAPE, before any launch, when the plan's workspace
+ *     (about L D 16 + D Npad 4 bytes, plus L D 4 with the centre test) exceeds
+ *     PZ_NOALLOC_SCRATCH_BYTES; PZ_E_UNSUPPORTED for an atmosphere with
+ *     continuum scattering.
+ *   - All calls on one GPU share that GPU's array, whatever the plan: calls
+ *     that overlap in time on one GPU (other streams or threads) race and give
+ *     wrong results.  Calls queued on one stream are ordered and safe.
+ *   - It leaves the plan's own workspace untouched, so a following
+ *     synth_backward does not reuse this call's opacity. */
+#define PZ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int synth_forward_noalloc(const pz_plan* plan, const pz_atmos* atm, const pz_params* par, float* F, float* Fc,
+                          pz_stream stream);
 
 /* Largest number of iterations any pixel used in the last scattering forward
  * (total branch, continuum branch) and adjoint solve on this plan: iters[3]

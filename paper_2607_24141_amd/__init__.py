@@ -32,6 +32,7 @@ PZ_FLAG_SCATTERING = 2
 PZ_MODE_FWD = 1
 PZ_MODE_FWD_BWD = 2
 PZ_MAX_DEPTH = 80
+PZ_NOALLOC_SCRATCH_BYTES = 64 << 20
 PZ_N_STAGES = 7
 STAGES = ("populations", "line_params", "opacity", "flux", "reverse_scan", "gather", "reduce")
 
@@ -50,7 +51,7 @@ class pz_lines(C.Structure):
                 ("log_gstark", _c_double_p), ("log_gvdw", _c_double_p)]
 
 
-ABI_VERSION = 4   # PZ_VERSION of include/pz.h the structures below follow
+ABI_VERSION = 5   # PZ_VERSION of include/pz.h the structures below follow
 
 
 class pz_options(C.Structure):
@@ -106,6 +107,7 @@ def _load():
     lib.pz_plan_info.argtypes = [C.c_void_p] + [_c_int_p] * 5 + [C.POINTER(C.c_int64)]
     lib.synth_forward.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
                                   C.c_void_p, C.c_void_p]
+    lib.synth_forward_noalloc.argtypes = lib.synth_forward.argtypes
     lib.synth_backward.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.pz_line_opacity.argtypes = [C.c_void_p, C.POINTER(pz_atmos), C.POINTER(pz_params), C.c_void_p,
@@ -144,7 +146,7 @@ def _load():
     lib.pz_groups_reduce.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.pz_wmse_seed.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                  C.c_void_p, C.c_int32, C.c_void_p]
-    for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_backward", "pz_line_opacity",
+    for name in ("pz_plan_create", "pz_plan_info", "pz_plan_invalidate", "pz_plan_profile", "pz_plan_profile_read", "pz_chi2_seed", "synth_forward", "synth_forward_noalloc", "synth_backward", "pz_line_opacity",
                  "pz_debug_opacity_adjoint", "pz_debug_formal_solve", "pz_batch_create", "synth_batch", "pz_autotune",
                  "pz_inst_create", "pz_inst_forward", "pz_inst_backward", "pz_correction_groups",
                  "pz_select_lines", "pz_scatter_iterations", "pz_groups_create", "pz_groups_info", "pz_groups_expand", "pz_groups_reduce", "pz_wmse_seed"):
@@ -156,7 +158,7 @@ lib = _load()
 
 EXPORTS = ("pz_version", "pz_last_error", "pz_plan_create", "pz_plan_destroy", "pz_plan_info", "pz_plan_invalidate",
            "pz_plan_profile", "pz_plan_profile_read",
-           "synth_forward", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_opacity_adjoint",
+           "synth_forward", "synth_forward_noalloc", "synth_backward", "pz_chi2_seed", "pz_line_opacity", "pz_debug_opacity_adjoint",
            "pz_debug_formal_solve",
            "pz_batch_create", "pz_batch_destroy", "synth_batch", "pz_autotune",
            "pz_inst_create", "pz_inst_destroy", "pz_inst_forward", "pz_inst_backward",
@@ -362,6 +364,11 @@ class Params:
 # ------------------------------------------------------------- entry points
 def synth_forward(plan, atm, par, F, Fc, stream=None):
     _check(lib.synth_forward(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(F), _ptr(Fc), _stream(stream)))
+
+
+def synth_forward_noalloc(plan, atm, par, F, Fc, stream=None):
+    _check(lib.synth_forward_noalloc(plan.handle, C.byref(atm.c), C.byref(par.c), _ptr(F), _ptr(Fc),
+                                     _stream(stream)))
 
 
 def synth_backward(plan, atm, par, dL_dF, g_loggf, g_damp, g_abund, g_xi, dL_dFc=None, stream=None):

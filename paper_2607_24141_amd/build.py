@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpz.so")
-SOURCES = ["pz_api.hip", "pz_kernels.hip", "pz_batch.hip", "pz_instrument.hip", "pz_calib.hip"]
+SOURCES = ["pz_api.hip", "pz_kernels.hip", "pz_batch.hip", "pz_instrument.hip", "pz_calib.hip", "pz_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

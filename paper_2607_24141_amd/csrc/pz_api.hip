@@ -430,6 +430,11 @@ namespace pz {
 
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
+int clear_error() {
+    g_err.clear();
+    return PZ_OK;
+}
+
 int check_atmos(const pz_plan* plan, const pz_atmos* atm) {
     if (!atm) return fail(PZ_E_INVALID_ARG, "atmosphere is NULL");
     if (atm->D != plan->D) return fail(PZ_E_SHAPE, "atmosphere has D=%d, plan expects %d", atm->D, plan->D);

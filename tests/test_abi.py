@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(pz):
 
 
 def test_version(pz):
-    assert pz.pz_version() == pz.ABI_VERSION == 4
+    assert pz.pz_version() == pz.ABI_VERSION == 5
 
 
 def _lines(pz, L=3, **over):
