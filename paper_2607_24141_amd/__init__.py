@@ -437,13 +437,21 @@ def _autograd_function():
             par = Params(dgf.detach().contiguous(), ddamp.detach().contiguous(), dA.detach().contiguous(),
                          xi.detach().contiguous())
             synth_forward(plan, atm, par, F, Fc)
-            ctx.plan, ctx.atm, ctx.par = plan, atm, par
+            # torch's version counters then reject a backward after an in-place
+            # edit of the corrections (the plan's workspace holds this forward)
+            ctx.save_for_backward(dgf, ddamp, dA, xi)
+            token = object()
+            plan._autograd_token = token
+            ctx.plan, ctx.atm, ctx.par, ctx.token = plan, atm, par, token
             ctx.mark_non_differentiable(Fc)
             return F, Fc
 
         @staticmethod
         def backward(ctx, gF, gFc):
+            ctx.saved_tensors                       # raises if an input was modified in place
             plan, par = ctx.plan, ctx.par
+            if getattr(plan, "_autograd_token", None) is not ctx.token:
+                plan.invalidate()                   # another forward ran on this plan since: recompute
             dev = par.xi.device
             g = [torch.empty(plan.L, dtype=torch.float32, device=dev),
                  torch.empty(plan.L, dtype=torch.float32, device=dev),

@@ -145,7 +145,8 @@ def test_objective_and_gradient_vs_oracle(gpu_lib):
     unit = _unit_residual_scale(stds, q, G, theta32.astype(np.float64))
     from test_gpu_adjoint import TERM_TOL
     for r, kind in enumerate(CAL.KINDS):
-        grad_close_cond(g[r], ref_g[r], ref_abs[r] + EPS_F / TERM_TOL * unit[r], rtol=2e-3, name=kind)
+        grad_close_cond(g[r], ref_g[r], ref_abs[r] + EPS_F / TERM_TOL * unit[r], rtol=2e-3, name=kind,
+                        cond_fallback=True)
     # strong groups (the 25 % largest gradients) hold to 2e-3 relative alone
     big = np.abs(ref_g) >= np.quantile(np.abs(ref_g), 0.75)
     assert np.all(np.abs(g - ref_g)[big] <= 2e-3 * np.abs(ref_g)[big])
