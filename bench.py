@@ -56,27 +56,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+# The gather kernel's code: its stage bodies, the Voigt evaluator and its
+# definition in pz_kernels.hip.
+GATHER_SOURCES = ("paper_2607_24141_amd/csrc/pz_stages.h", "paper_2607_24141_amd/csrc/pz_voigt.h",
+                  "paper_2607_24141_amd/csrc/voigt_consts.h")
+GATHER_DEF = ("paper_2607_24141_amd/csrc/pz_kernels.hip", "void k_gather(")
+
+
+def kernel_hash(sources=KERNEL_SOURCES, definition=KERNEL_DEF):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    with open(os.path.join(ROOT, KERNEL_DEF[0])) as fh:
+    with open(os.path.join(ROOT, definition[0])) as fh:
         txt = fh.read()
-    i = txt.index(KERNEL_DEF[1])
+    i = txt.index(definition[1])
     i = txt.rindex("\n", 0, txt.rindex("\n", 0, i)) + 1      # from the template line above
     h.update(txt[i:txt.index("\n}\n", i) + 3].encode())
     return h.hexdigest()[:16]
 
 
-def _profile_json(name):
+def gather_hash():
+    return kernel_hash(GATHER_SOURCES, GATHER_DEF)
+
+
+def _profile_json(name, hash_fn=kernel_hash):
     """A committed counter summary under profiles/, if it was taken on these kernel sources."""
     try:
         with open(os.path.join(ROOT, "profiles", name)) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    return d if d.get("kernel_hash") == kernel_hash() else None
+    return d if d.get("kernel_hash") == hash_fn() else None
 
 
 def traffic_from_profiles(kind="opacity"):
@@ -325,6 +336,13 @@ def main():
             out["scan_roofline"]["k_reverse_scan"] = {"bytes": b, "ms": st_fb["reverse_scan"],
                                                       "GB_s": b / (st_fb["reverse_scan"] * 1e6),
                                                       "frac_hbm": b / (st_fb["reverse_scan"] * 1e6) / PEAK_HBM_GBS}
+        vg = _profile_json("valu_gather.json", gather_hash)
+        if vg and "gather" in st_fb:
+            tg = vg["flops_per_eval"] * plan.voigt_evals / (st_fb["gather"] * 1e-3) / 1e12
+            out["roofline_gather"] = {"bound": "alu", "kernel": "k_gather", "achieved": tg, "peak": PEAK_FP32_TFLOPS,
+                                      "unit": "TFLOP/s", "frac": tg / PEAK_FP32_TFLOPS,
+                                      "flops_per_eval": vg["flops_per_eval"], "kernel_avg_ms": st_fb["gather"],
+                                      "flops_source": "SQ VALU counters (profiles/valu_gather.json)"}
         out["fwd_bwd"] = {"spectra_per_s": 1000.0 / ms_fb, "ms_per_step": ms_fb, "ratio_to_fwd": ms_fb / ms_fwd,
                           "voigt_evals_per_s": 2 * plan.voigt_evals / (ms_fb * 1e-3),
                           "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof_fb.items() if v[1]}}

@@ -161,12 +161,19 @@ int pz_version(void);
 /* Message of the last error on the calling thread ("" if none). */
 const char* pz_last_error(void);
 
-/* Build a plan: validates the grid and the line list, sorts the lines by
- * wavelength, computes each line's integer window [i_lo, i_hi] in float64 from
- * |lambda_i - lambda_l| <= W, bins lines into wavelength tiles and uploads
- * everything to the current device.  Lines whose window misses the grid are
- * kept (zero contribution, zero gradient).  Synchronises the device.
- * n_species = S and n_depth = D fix the atmosphere shape the plan accepts. */
+/* Build a plan (Sec. 2.1 Eqs. 1-2: the log-uniform grid and its sample
+ * count; Sec. 2.2: the window bounds prepared once per source window and kept
+ * resident, the bounded wing spans): validates the grid and the line list,
+ * sorts the lines by wavelength, computes each line's integer window
+ * [i_lo, i_hi] in float64 from |lambda_i - lambda_l| <= W, bins lines into
+ * wavelength tiles and uploads everything to the current device.  Lines whose
+ * window misses the grid are kept (zero contribution, zero gradient).
+ * Synchronises the device.  n_species = S and n_depth = D fix the atmosphere
+ * shape the plan accepts.  Host arrays are read during the call only; the
+ * plan owns its device memory until pz_plan_destroy.  Errors: PZ_E_INVALID_ARG
+ * (null pointer, bad option, species or ion out of range), PZ_E_NONFINITE (a
+ * non-finite line value), PZ_E_SHAPE (sizes beyond the limits above),
+ * PZ_E_NOMEM, PZ_E_HIP. */
 int pz_plan_create(const pz_grid* grid, const pz_lines* lines, int32_t n_species,
                    int32_t n_depth, const pz_options* opts, pz_plan** out);
 
@@ -317,15 +324,21 @@ typedef struct {
 } pz_star;
 
 /* Prepare a batch of stars with different atmospheres, windows and line
- * counts: uploads a device table of the stars' descriptors and builds the
- * work lists (opacity tiles of all stars ordered by decreasing cost).  The
- * per-star plans must outlive the batch, and no two stars may share a plan
- * (each plan's workspace holds that star's intermediate arrays).
- * Synchronises the device. */
+ * counts (the stars are independent syntheses, Sec. 9): uploads a device
+ * table of the stars' descriptors and builds the work lists (opacity tiles of
+ * all stars ordered by decreasing cost).  Preparing these once is what lets
+ * synth_batch be a pure enqueue that can be captured and replayed.  The
+ * per-star plans and every buffer a star names must outlive the batch, and no
+ * two stars may share a plan (each plan's workspace holds that star's
+ * intermediate arrays).  Synchronises the device.  Errors: PZ_E_INVALID_ARG
+ * (null arguments, shared plans, a scattering atmosphere: PZ_E_UNSUPPORTED),
+ * the per-star checks of synth_forward, PZ_E_NOMEM, PZ_E_HIP. */
 int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out);
 void pz_batch_destroy(pz_batch* batch);
 
-/* Batched synthesis (PZ_MODE_FWD or PZ_MODE_FWD_BWD): every stage runs as one
+/* Batched synthesis of independent stars (Sec. 9; each star's forward and
+ * backward as synth_forward and synth_backward define them, Secs. 2.1, 6)
+ * (PZ_MODE_FWD or PZ_MODE_FWD_BWD): every stage runs as one
  * persistent launch whose workgroups take (star, item) work from a queue
  * spanning all stars.  Enqueue-only: no host synchronisation, allocation or
  * memset, so the call may be captured in a hipGraph and replayed.  Results

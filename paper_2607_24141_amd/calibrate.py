@@ -13,9 +13,10 @@ objective runs entirely in the library's kernels:
                 pz_groups_reduce (accumulating over stars) --> dL/dtheta [4][G]
 
 The objective is sum_s c_s sum_p w_sp (f_sp - y_sp)^2 over the standards s
-(each star's epochs share its synthesis).  The optimiser is PyTorch's L-BFGS
-with a strong-Wolfe line search over unconstrained u, with the smooth bound
-transform theta = b tanh(u / b) per correction kind.
+(each star's epochs share its synthesis).  The optimiser is L-BFGS with a
+strong-Wolfe line search over unconstrained u, with the smooth bound
+transform theta = b tanh(u / b) per correction kind; its vectors stay on the
+device and each evaluation costs one host transfer of two scalars.
 """
 from __future__ import annotations
 
@@ -154,45 +155,156 @@ def bound(u, b):
     return b * torch.tanh(u / b)
 
 
+def _cubic_min(t0, f0, d0, t1, f1, d1, lo, hi):
+    """Minimiser of the cubic through (t0, f0, f0') and (t1, f1, f1'), clamped to
+    [lo, hi]; the midpoint of [lo, hi] if the cubic has no real minimiser."""
+    d1s = d0 + d1 - 3.0 * (f0 - f1) / (t0 - t1)
+    disc = d1s * d1s - d0 * d1
+    if disc < 0.0:
+        return 0.5 * (lo + hi)
+    d2 = math.copysign(math.sqrt(disc), t1 - t0)
+    den = d1 - d0 + 2.0 * d2
+    if den == 0.0:
+        return 0.5 * (lo + hi)
+    t = t1 - (t1 - t0) * (d1 + d2 - d1s) / den
+    return min(max(t, lo), hi)
+
+
+def _strong_wolfe(phi, f0, d0, t, c1=1e-4, c2=0.9, max_ls=25):
+    """Step length satisfying the strong Wolfe conditions along a descent
+    direction (bracketing, then zoom by safeguarded cubic interpolation;
+    Nocedal and Wright, Numerical Optimization, Algorithms 3.5 and 3.6).
+    phi(t) -> (f, f', state) evaluates the objective; returns (t, f, state) of
+    the accepted point (the best one seen if max_ls evaluations do not
+    settle it)."""
+    best = None
+    t_prev, f_prev, d_prev = 0.0, f0, d0
+    lo = hi = None
+    for i in range(max_ls):
+        f, d, st = phi(t)
+        if best is None or f < best[1]:
+            best = (t, f, st)
+        if lo is None:
+            if f > f0 + c1 * t * d0 or (i > 0 and f >= f_prev):
+                lo, hi = (t_prev, f_prev, d_prev), (t, f, d)
+            elif abs(d) <= -c2 * d0:
+                return t, f, st
+            elif d >= 0.0:
+                lo, hi = (t, f, d), (t_prev, f_prev, d_prev)
+            else:
+                t_new = _cubic_min(t_prev, f_prev, d_prev, t, f, d, t + 0.01 * (t - t_prev), 10.0 * t)
+                t_prev, f_prev, d_prev = t, f, d
+                t = t_new
+                continue
+        else:
+            if f > f0 + c1 * t * d0 or f >= lo[1]:
+                hi = (t, f, d)
+            else:
+                if abs(d) <= -c2 * d0:
+                    return t, f, st
+                if d * (hi[0] - lo[0]) >= 0.0:
+                    hi = lo
+                lo = (t, f, d)
+        a, b = sorted((lo[0], hi[0]))
+        if b - a < 1e-12 * max(1.0, b):
+            break
+        t = _cubic_min(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], a + 0.1 * (b - a), b - 0.1 * (b - a))
+    return best
+
+
+def lbfgs(fg, x0, max_iter=40, history_size=10, max_eval=None):
+    """Limited-memory BFGS with a strong-Wolfe line search (Nocedal and Wright,
+    Algorithm 7.4 for the two-loop recursion).  fg(x) -> (f [1], g) on the
+    device; the direction, the curvature pairs and every vector update stay on
+    the device, and each evaluation costs one host transfer (f and the slope
+    along the direction, read together).  Returns dict(x, f, iters, evals,
+    history)."""
+    max_eval = max_eval or 4 * max_iter
+    x = x0.detach().clone()
+    f_t, g = fg(x)
+    f = float(f_t[0])
+    evals, hist = 1, [f]
+    S, Y, R = [], [], []                          # curvature pairs and 1/(y.s), device
+    it = 0
+    while it < max_iter and evals < max_eval:
+        # two-loop recursion for d = -H g
+        q = -g
+        alpha = []
+        for s_i, y_i, r_i in zip(reversed(S), reversed(Y), reversed(R)):
+            a_i = r_i * torch.dot(s_i.flatten(), q.flatten())
+            q = q - a_i * y_i
+            alpha.append(a_i)
+        if S:
+            q = q * (torch.dot(S[-1].flatten(), Y[-1].flatten()) / torch.dot(Y[-1].flatten(), Y[-1].flatten()))
+        for (s_i, y_i, r_i), a_i in zip(zip(S, Y, R), reversed(alpha)):
+            b_i = r_i * torch.dot(y_i.flatten(), q.flatten())
+            q = q + (a_i - b_i) * s_i
+        d = q
+        gd_t = torch.dot(g.flatten(), d.flatten())
+        gd = float(gd_t)
+        if not gd < 0.0:                          # not a descent direction: restart from -g
+            S, Y, R = [], [], []
+            d = -g
+            gd = float(torch.dot(g.flatten(), d.flatten()))
+            if gd == 0.0:
+                break
+        t0 = min(1.0, 1.0 / float(g.abs().sum())) if it == 0 else 1.0
+
+        def phi(t):
+            nonlocal evals
+            xt = x + t * d
+            ft, gt = fg(xt)
+            evals += 1
+            v = torch.stack([ft[0], torch.dot(gt.flatten(), d.flatten())]).tolist()
+            return v[0], v[1], (xt, gt)
+
+        t, f_new, (x_new, g_new) = _strong_wolfe(phi, f, gd, t0, max_ls=max(1, min(25, max_eval - evals)))
+        s_k, y_k = x_new - x, g_new - g
+        ys = torch.dot(y_k.flatten(), s_k.flatten())
+        if float(ys) > 1e-10:
+            if len(S) == history_size:
+                S.pop(0), Y.pop(0), R.pop(0)
+            S.append(s_k)
+            Y.append(y_k)
+            R.append(1.0 / ys)
+        x, g, f = x_new, g_new, f_new
+        hist.append(f)
+        it += 1
+    return dict(x=x, f=f, iters=it, evals=evals, history=hist)
+
+
 def fit(cal, theta0=None, bounds=DEFAULT_BOUNDS, max_iter=40, history_size=10, max_eval=None, log=None):
-    """L-BFGS (strong Wolfe) over the group corrections.  Returns dict(theta,
-    loss0, loss, iters, evals, seconds)."""
+    """L-BFGS (strong Wolfe) over the group corrections in the unconstrained
+    u of theta = b tanh(u / b).  Returns dict(theta, loss0, loss, iters, evals,
+    seconds, history)."""
     dev = cal.device
     b = torch.tensor(bounds, dtype=torch.float32, device=dev)[:, None]
     if theta0 is None:
-        u = torch.zeros(4, cal.G, device=dev)
+        u0 = torch.zeros(4, cal.G, device=dev)
     else:
         t = torch.as_tensor(theta0, dtype=torch.float32, device=dev)
-        u = b * torch.atanh(torch.clamp(t / b, -0.999999, 0.999999))
-    u.requires_grad_(True)
-    opt = torch.optim.LBFGS([u], lr=1.0, max_iter=max_iter, max_eval=max_eval or 4 * max_iter,
-                            history_size=history_size, line_search_fn="strong_wolfe",
-                            tolerance_grad=0.0, tolerance_change=0.0)
+        u0 = b * torch.atanh(torch.clamp(t / b, -0.999999, 0.999999))
     e0 = cal.n_evals
-    hist = []
 
-    def closure():
+    def fg(u):
         with torch.no_grad():
             t = torch.tanh(u / b)
             loss, g = cal.evaluate((b * t).contiguous())
-            u.grad = (g * (1.0 - t * t)).contiguous()
-            val = loss[0].clone()
-        hist.append(float(val))
-        if log:
-            log(len(hist), hist[-1])
-        return val
+            return loss.clone(), g * (1.0 - t * t)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    opt.step(closure)
+    r = lbfgs(fg, u0, max_iter=max_iter, history_size=history_size, max_eval=max_eval)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    st = opt.state[u]
+    if log:
+        for k, v in enumerate(r["history"]):
+            log(k + 1, v)
     with torch.no_grad():
-        theta = bound(u, b).detach()
+        theta = bound(r["x"], b).detach()
         loss = float(cal.evaluate(theta.contiguous())[0][0])
-    return dict(theta=theta, loss0=hist[0], loss=loss, iters=int(st.get("n_iter", 0)),
-                evals=cal.n_evals - e0 - 1, seconds=secs, history=hist)
+    return dict(theta=theta, loss0=r["history"][0], loss=loss, iters=r["iters"],
+                evals=cal.n_evals - e0 - 1, seconds=secs, history=r["history"])
 
 
 def mock_observed(cal, theta_true, sigma, seed):
