@@ -516,9 +516,21 @@ def main():
         ms_if, _ = timed(lambda: pz.pz_inst_forward(inst, F, Fc, vel, None, None, fobs), args.steps, args.warmup, torch)
         ms_ib, _ = timed(lambda: pz.pz_inst_backward(inst, F, Fc, vel, iseed, dFi, dFci, gv), args.steps,
                          args.warmup, torch)
-        out["instrument"] = {"observed_pixels": inst.P, "native_pixels": int(F.numel()),
-                             "fwd_us_per_flux_pair": ms_if * 1e3, "bwd_us_per_flux_pair": ms_ib * 1e3}
         inst.destroy()
+        # the same with the rotation stage (v sin i up to 40 km/s, limb darkening 0.6)
+        rinst = pz.Instrument(wl.grid, lam_obs, sig, vbmax, vrot_max_kms=40.0, limb_eps=0.6)
+        rvel = torch.tensor([12.0, 6.0, 25.0], dtype=torch.float32, device=dev)
+        rgv = torch.empty(3, dtype=torch.float32, device=dev)
+        ms_rf, _ = timed(lambda: pz.pz_inst_forward(rinst, F, Fc, rvel, None, None, fobs), args.steps, args.warmup,
+                         torch)
+        ms_rb, _ = timed(lambda: pz.pz_inst_backward(rinst, F, Fc, rvel, iseed, dFi, dFci, rgv), args.steps,
+                         args.warmup, torch)
+        rinst.destroy()
+        out["instrument"] = {"observed_pixels": inst.P, "native_pixels": int(F.numel()),
+                             "fwd_us_per_flux_pair": ms_if * 1e3, "bwd_us_per_flux_pair": ms_ib * 1e3,
+                             "with_rotation": {"vsini_kms": 25.0, "vrot_max_kms": 40.0,
+                                               "fwd_us_per_flux_pair": ms_rf * 1e3,
+                                               "bwd_us_per_flux_pair": ms_rb * 1e3}}
 
     # ---- line calibration (Sec. 6): two stars, three spectra, shared group corrections, L-BFGS
     if "calibration" in modes:

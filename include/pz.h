@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define PZ_VERSION 5
+#define PZ_VERSION 6
 #define PZ_MAX_DEPTH 80
 
 #define PZ_OK 0
@@ -356,13 +356,22 @@ int pz_autotune(const pz_grid* grid, const pz_lines* lines, int32_t n_species, i
 
 /* ---------------------------------------------------------------- instrument
  * The instrument operator of Eq. 31 (Eq. 9): both native fluxes pass through
- * a Gaussian broadening B(v_b) on the logarithmic synthesis grid, a Doppler
- * shift S(v_r) and a Gaussian line-spread function sampled at observed
- * pixels K before their ratio, f_p = {K S B F}_p / {K S B F_c}_p.
+ * a Gaussian broadening B(v_b) on the logarithmic synthesis grid, optionally
+ * a rotational broadening R(v sin i) (Sec. 7 mentions a GPU-resident
+ * rotational kernel and leaves it undefined), a Doppler shift S(v_r) and a
+ * Gaussian line-spread function sampled at observed pixels K before their
+ * ratio, f_p = {K S R B F}_p / {K S R B F_c}_p.
  * Discretisation (x = ln lambda, native pixel spacing h = ln(1 + 1/R)):
  *   B: normalised Gaussian of sigma = v_b / (c h) pixels over a fixed support
  *      of +-J pixels, J = ceil(4 vb_max / (c h)), renormalised at the grid
  *      ends (v_b below 1e-3 c h acts as the identity, with zero gradient);
+ *   R: (only when vrot_max_kms > 0) weights r_k = the integral over the pixel
+ *      cell [k - 1/2, k + 1/2] of the classical rotation profile of a disc
+ *      with linear limb darkening I(mu) = 1 - eps + eps mu, of half-width
+ *      s = v sin i / (c h) pixels, over a fixed support of +-JR pixels,
+ *      JR = ceil(vrot_max / (c h) + 1/2), renormalised at the grid ends;
+ *      v sin i <= 0 is the identity; a v sin i above vrot_max is cut to the
+ *      support and renormalised (it is read on the device, so not checked);
  *   S: value at fractional pixel i - ln(1 + v_r/c)/h by linear interpolation,
  *      the index clamped to the grid;
  *   K: normalised Gaussian of the pixel's LSF width in ln lambda over
@@ -375,6 +384,8 @@ typedef struct {
     const double* lsf_sigma_ln; /* [P] host: Gaussian LSF width in ln lambda (> 0)           */
     double lsf_trunc;           /* LSF support half-width in widths; 0 = 4                   */
     double vb_max_kms;          /* > 0: the largest broadening used; sets B's support        */
+    double vrot_max_kms;        /* >= 0: the largest v sin i used; 0 = no rotation stage     */
+    double limb_eps;            /* linear limb-darkening coefficient in [0, 1] (rotation)    */
 } pz_inst_desc;
 
 /* Build an instrument for the synthesis grid: LSF supports (each must lie
@@ -386,15 +397,18 @@ int pz_inst_create(const pz_grid* grid, const pz_inst_desc* desc, pz_inst** out)
 /* Release an instrument (NULL is a no-op).  Synchronises the device. */
 void pz_inst_destroy(pz_inst* inst);
 
-/* f = K S B F / K S B Fc.  F, Fc: [N] device float32 native fluxes; vel:
- * [2] device float32 (v_r, v_b) in km/s; outputs [P] device float32, any of
- * KF (K S B F), KFc, f may be NULL but not all.  Enqueue-only. */
+/* f = K S R B F / K S R B Fc.  F, Fc: [N] device float32 native fluxes; vel:
+ * device float32 velocities in km/s, [2] (v_r, v_b), or [3] (v_r, v_b,
+ * v sin i) for an instrument with a rotation stage; outputs [P] device
+ * float32, any of KF (K S R B F), KFc, f may be NULL but not all.
+ * Enqueue-only. */
 int pz_inst_forward(const pz_inst* inst, const float* F, const float* Fc, const float* vel, float* KF, float* KFc,
                     float* f, pz_stream stream);
 
 /* Vector-Jacobian product of the map above for the seed dL_df [P]: writes
- * dL_dF, dL_dFc [N] and g_vel [2] = (dL/dv_r, dL/dv_b) (device float32; any
- * may be NULL but not all).  The velocity sums run in a fixed order.  Uses
+ * dL_dF, dL_dFc [N] and g_vel = (dL/dv_r, dL/dv_b), and dL/d(v sin i) as a
+ * third entry with a rotation stage (device float32; any may be NULL but
+ * not all).  The velocity sums run in a fixed order.  Uses
  * the instrument's workspace: calls on one instrument must not overlap.
  * Enqueue-only; no allocation, so it may be captured in a hipGraph. */
 int pz_inst_backward(const pz_inst* inst, const float* F, const float* Fc, const float* vel, const float* dL_df,

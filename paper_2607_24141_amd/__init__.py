@@ -51,7 +51,7 @@ class pz_lines(C.Structure):
                 ("log_gstark", _c_double_p), ("log_gvdw", _c_double_p)]
 
 
-ABI_VERSION = 5   # PZ_VERSION of include/pz.h the structures below follow
+ABI_VERSION = 6   # PZ_VERSION of include/pz.h the structures below follow
 
 
 class pz_options(C.Structure):
@@ -62,7 +62,8 @@ class pz_options(C.Structure):
 
 class pz_inst_desc(C.Structure):
     _fields_ = [("P", C.c_int32), ("lam_obs_nm", _c_double_p), ("lsf_sigma_ln", _c_double_p),
-                ("lsf_trunc", C.c_double), ("vb_max_kms", C.c_double)]
+                ("lsf_trunc", C.c_double), ("vb_max_kms", C.c_double), ("vrot_max_kms", C.c_double),
+                ("limb_eps", C.c_double)]
 
 
 class pz_atmos(C.Structure):
@@ -574,19 +575,23 @@ def pz_wmse_seed(f, y, w, c, dL_df=None, loss=None, accumulate=False, stream=Non
 class Instrument:
     """pz_inst_create / pz_inst_destroy: the instrument operator of Eq. 31 for a
     synthesis grid, observed pixel centres (nm), LSF widths (ln lambda) and the
-    largest broadening velocity (km/s)."""
+    largest broadening velocity (km/s); with vrot_max_kms > 0 also a rotation
+    stage (largest v sin i, linear limb-darkening coefficient limb_eps), whose
+    velocity vectors then hold (v_r, v_b, v sin i)."""
 
-    def __init__(self, grid, lam_obs_nm, lsf_sigma_ln, vb_max_kms, lsf_trunc=0.0):
+    def __init__(self, grid, lam_obs_nm, lsf_sigma_ln, vb_max_kms, lsf_trunc=0.0, vrot_max_kms=0.0, limb_eps=0.6):
         import numpy as np
         self._lam = np.ascontiguousarray(lam_obs_nm, dtype=np.float64)
         self._sig = np.ascontiguousarray(lsf_sigma_ln, dtype=np.float64)
         g = pz_grid(float(grid.lam_first_nm), float(grid.R), int(grid.N))
         d = pz_inst_desc(int(self._lam.size), self._lam.ctypes.data_as(_c_double_p),
-                         self._sig.ctypes.data_as(_c_double_p), float(lsf_trunc), float(vb_max_kms))
+                         self._sig.ctypes.data_as(_c_double_p), float(lsf_trunc), float(vb_max_kms),
+                         float(vrot_max_kms), float(limb_eps))
         h = C.c_void_p()
         _check(lib.pz_inst_create(C.byref(g), C.byref(d), C.byref(h)))
         self.handle = h
         self.N, self.P = int(grid.N), int(self._lam.size)
+        self.n_vel = 3 if vrot_max_kms > 0 else 2
 
     def destroy(self):
         if getattr(self, "handle", None):
@@ -601,12 +606,17 @@ class Instrument:
 
 
 def pz_inst_forward(inst, F, Fc, vel, KF=None, KFc=None, f=None, stream=None):
-    """f = K S B F / K S B Fc on torch's current stream (device float32 tensors)."""
+    """f = K S R B F / K S R B Fc on torch's current stream (device float32
+    tensors; vel holds inst.n_vel velocities)."""
+    if vel.numel() < inst.n_vel:
+        raise ValueError("vel needs %d entries for this instrument" % inst.n_vel)
     _check(lib.pz_inst_forward(inst.handle, _ptr(F), _ptr(Fc), _ptr(vel), _ptr(KF), _ptr(KFc), _ptr(f),
                                _stream(stream)))
 
 
 def pz_inst_backward(inst, F, Fc, vel, dL_df, dL_dF=None, dL_dFc=None, g_vel=None, stream=None):
-    """VJP of pz_inst_forward's f for the seed dL_df."""
+    """VJP of pz_inst_forward's f for the seed dL_df (g_vel holds inst.n_vel entries)."""
+    if vel.numel() < inst.n_vel or (g_vel is not None and g_vel.numel() < inst.n_vel):
+        raise ValueError("vel and g_vel need %d entries for this instrument" % inst.n_vel)
     _check(lib.pz_inst_backward(inst.handle, _ptr(F), _ptr(Fc), _ptr(vel), _ptr(dL_df), _ptr(dL_dF),
                                 _ptr(dL_dFc), _ptr(g_vel), _stream(stream)))

@@ -1,14 +1,24 @@
 // Instrument operator of Eq. 31 (and Eq. 9) on the GPU: Gaussian broadening
-// B(v_b) on the logarithmic synthesis grid, Doppler shift S(v_r), and a
-// Gaussian line-spread function sampled at the observed pixels (K), applied
-// to both the total and the continuum flux before their ratio,
-//     f_p = {K S B F}_p / {K S B F_c}_p ,
-// with the vector-Jacobian product for F, F_c, v_r and v_b.
+// B(v_b) on the logarithmic synthesis grid, an optional rotational broadening
+// R(v sin i) (Sec. 7 names a GPU-resident rotational kernel without defining
+// it), Doppler shift S(v_r), and a Gaussian line-spread function sampled at
+// the observed pixels (K), applied to both the total and the continuum flux
+// before their ratio,
+//     f_p = {K S R B F}_p / {K S R B F_c}_p ,
+// with the vector-Jacobian product for F, F_c, v_r, v_b and v sin i.
 //
 // Discretisation (x = ln lambda, native x_i = x_0 + i h):
 //   B: (B G)_i = sum_{|k|<=J} g_k G_{i-k} / Z_i, g_k = exp(-k^2 / (2 s^2)),
 //      s = v_b / (c h) pixels, Z_i the sum of the g_k whose G_{i-k} exists;
 //      J fixed at creation from the largest v_b.
+//   R: (R G)_i = sum_{|k|<=JR} r_k G_{i-k} / ZR_i, r_k the integral over the
+//      pixel cell [k - 1/2, k + 1/2] of the rotation profile of a linearly
+//      limb-darkened disc (limb-darkening coefficient eps) scaled to the
+//      half-width s = v sin i / (c h) pixels; the profile in y = u / s is
+//      [2 (1 - eps) sqrt(1 - y^2) + (pi eps / 2)(1 - y^2)] / [pi (1 - eps/3)]
+//      and its antiderivative is closed form, so r_k is a difference of two
+//      antiderivative values (taken in FP64); JR fixed at creation from the
+//      largest v sin i, ZR_i the sum of the r_k whose G_{i-k} exists.
 //   S: (S G)_i = (1 - r) G_{i+m} + r G_{i+m+1}, i - t = i + m + r,
 //      t = ln(1 + v_r/c) / h, m = floor(-t), indices clamped to the grid.
 //   K: (K H)_p = sum_i w_pi H_i / W_p over the pixels within T LSF widths,
@@ -32,8 +42,8 @@ int set_error(int code, const char* msg);
 using namespace pz;
 
 struct pz_inst {
-    int N, P, J, nblk;
-    double h;
+    int N, P, J, JR, nblk;
+    double h, eps;
     // per observed pixel: LSF support [lo, hi], centre c_p = lo + off, a_p
     int* lo;
     int* hi;
@@ -45,11 +55,14 @@ struct pz_inst {
     // workspace
     float* BF;     // [2][N] broadened total, continuum
     float* Z;      // [N]    broadening normalisers
+    float* RBF;    // [2][N] rotated R B F, R B Fc (rotation only)
+    float* ZR;     // [N]    rotation normalisers (rotation only)
+    float* dR;     // [2][N] dL/d(R B F) (rotation only)
     float* KW;     // [P]    LSF weight sums
     float* dY;     // [2][P] dL/d(K S B F) / W_p, both branches
     float* dS;     // [2][N] dL/d(S B F)
     float* dB;     // [2][N] dL/d(B F)
-    float* part;   // [2][nblk] partial sums of dL/dt and dL/ds
+    float* part;   // [3][nblk] partial sums of dL/dt, dL/ds and dL/ds_rot
     void* base;
 };
 
@@ -165,6 +178,98 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
     return r;
 }
 
+// Rotation profile of unit integral on |y| <= 1 and its antiderivative from -1.
+__device__ __forceinline__ double rot_pdf(double y, double eps) {
+    const double q = fmax(1.0 - y * y, 0.0);
+    return (2.0 * (1.0 - eps) * sqrt(q) + 0.5 * M_PI * eps * q) / (M_PI * (1.0 - eps / 3.0));
+}
+
+__device__ __forceinline__ double rot_cdf(double y, double eps) {
+    y = fmin(fmax(y, -1.0), 1.0);
+    const double a = (1.0 - eps) * (y * sqrt(fmax(1.0 - y * y, 0.0)) + asin(y));
+    const double b = 0.5 * M_PI * eps * (y - y * y * y / 3.0);
+    return (a + b) / (M_PI * (1.0 - eps / 3.0)) + 0.5;
+}
+
+// Rotation half-width in pixels from vel[2] (not positive: the identity).
+__device__ __forceinline__ double rot_width(const float* vel, double h) { return (double)vel[2] / (C_KMS * h); }
+
+// Cell weights r_k and dr_k/ds for k = 0..JR into LDS (the profile is even, so
+// r_{-k} = r_k).  A cell bound y = b/s moves as -y/s with s, unless clamped at +-1.
+__device__ __forceinline__ void load_rot(float* r, float* dr, int JR, double s, double eps) {
+    for (int k = threadIdx.x; k <= JR; k += blockDim.x) {
+        if (!(s > 0.0)) {
+            r[k] = k == 0 ? 1.0f : 0.0f;
+            dr[k] = 0.0f;
+            continue;
+        }
+        const double lo = (k - 0.5) / s, hi = (k + 0.5) / s;
+        r[k] = (float)(rot_cdf(hi, eps) - rot_cdf(lo, eps));
+        const double dhi = fabs(hi) < 1.0 ? rot_pdf(hi, eps) * (-hi / s) : 0.0;
+        const double dlo = fabs(lo) < 1.0 ? rot_pdf(lo, eps) * (-lo / s) : 0.0;
+        dr[k] = (float)(dhi - dlo);
+    }
+    __syncthreads();
+}
+
+// R for both branches; also the normalisers ZR.
+__global__ __launch_bounds__(TPB) void k_rotate(int N, int JR, double h, double eps, const float* vel,
+                                                const float* BF, float* RBF, float* ZR) {
+    extern __shared__ float rw[];
+    load_rot(rw, rw + JR + 1, JR, rot_width(vel, h), eps);
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= N) return;
+    float a = 0.0f, b = 0.0f, z = 0.0f;
+    const int k0 = max(-JR, i - (N - 1)), k1 = min(JR, i);     // 0 <= i - k < N
+    for (int k = k0; k <= k1; ++k) {
+        const float w = rw[abs(k)];
+        a = fmaf(w, BF[i - k], a);
+        b = fmaf(w, BF[N + i - k], b);
+        z += w;
+    }
+    const float iz = 1.0f / z;
+    RBF[i] = a * iz;
+    RBF[N + i] = b * iz;
+    ZR[i] = z;
+}
+
+// R^T: dB_j = sum_k r_k dR_{j+k} / ZR_{j+k}; and the per-block partial of
+// dL/ds_rot = sum_i dR_i d(R G)_i/ds with d(R G)_i/ds = sum_k r'_k (G_{i-k} - (R G)_i) / ZR_i
+// (the quotient rule with the normalised mean taken out of every tap first,
+// which keeps float cancellation small where G is nearly flat).
+__global__ __launch_bounds__(TPB) void k_rotate_T(int N, int JR, double h, double eps, const float* vel,
+                                                  const float* BF, const float* RBF, const float* ZR,
+                                                  const float* dR, float* dB, float* part) {
+    extern __shared__ float rw[];
+    __shared__ float red[TPB];
+    const float* dr = rw + JR + 1;
+    load_rot(rw, rw + JR + 1, JR, rot_width(vel, h), eps);
+    const int j = blockIdx.x * TPB + threadIdx.x;
+    float ds = 0.0f;
+    if (j < N) {
+        float a = 0.0f, b = 0.0f;
+        const int k0 = max(-JR, -j), k1 = min(JR, N - 1 - j);        // 0 <= j + k < N
+        for (int k = k0; k <= k1; ++k) {
+            const float w = rw[abs(k)] / ZR[j + k];
+            a = fmaf(w, dR[j + k], a);
+            b = fmaf(w, dR[N + j + k], b);
+        }
+        dB[j] = a;
+        dB[N + j] = b;
+        const float m0 = RBF[j], m1 = RBF[N + j];
+        float d0 = 0.0f, d1 = 0.0f;
+        const int q0 = max(-JR, j - (N - 1)), q1 = min(JR, j);       // 0 <= j - k < N
+        for (int k = q0; k <= q1; ++k) {
+            const float w = dr[abs(k)];
+            d0 = fmaf(w, BF[j - k] - m0, d0);
+            d1 = fmaf(w, BF[N + j - k] - m1, d1);
+        }
+        ds = (dR[j] * d0 + dR[N + j] * d1) / ZR[j];
+    }
+    const float tot = block_sum(ds, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
 // S^T, and the per-block partial of dL/dt = sum_i dS_i d(S B F)_i/dt,
 // d(S G)_i/dt = -(G_{i+m+1} - G_{i+m}) where neither index is clamped.
 __global__ __launch_bounds__(TPB) void k_shift_T(int N, double h, const float* vel, const float* BF, const float* dS,
@@ -247,21 +352,25 @@ __global__ __launch_bounds__(TPB) void k_broaden_T(int N, int J, double h, const
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// One workgroup: fixed-order sums of the partials -> dL/dv_r, dL/dv_b.
-__global__ __launch_bounds__(TPB) void k_vel_final(int nblk, double h, const float* vel, const float* part,
+// One workgroup: fixed-order sums of the partials -> dL/dv_r, dL/dv_b and,
+// with rotation, dL/d(v sin i).
+__global__ __launch_bounds__(TPB) void k_vel_final(int nblk, int rot, double h, const float* vel, const float* part,
                                                    float* g_vel) {
     __shared__ float red[TPB];
     const Vel v = velocities(vel, h);
-    float a = 0.0f, b = 0.0f;
+    float a = 0.0f, b = 0.0f, c = 0.0f;
     for (int k = threadIdx.x; k < nblk; k += TPB) {
         a += part[k];
         b += part[nblk + k];
+        if (rot) c += part[2 * nblk + k];
     }
     const float dt = block_sum(a, red);
     const float ds = block_sum(b, red);
+    const float dsr = rot ? block_sum(c, red) : 0.0f;
     if (threadIdx.x == 0) {
         g_vel[0] = (float)((double)dt / (h * (C_KMS + (double)vel[0])));     // t = ln(1 + v_r/c) / h
         g_vel[1] = v.s_clamped ? 0.0f : (float)((double)ds / (C_KMS * h));  // s = v_b / (c h)
+        if (rot) g_vel[2] = (float)((double)dsr / (C_KMS * h));             // s_rot = v sin i / (c h)
     }
 }
 
@@ -299,6 +408,14 @@ int pz_inst_create(const pz_grid* grid, const pz_inst_desc* d, pz_inst** out) {
     const double Jd = std::ceil(4.0 * d->vb_max_kms / C_KMS / h);
     if (Jd > MAX_J) return set_error(PZ_E_INVALID_ARG, "vb_max_kms gives a broadening support above 1024 pixels");
     const int J = (int)Jd;
+    if (!(d->vrot_max_kms >= 0.0) || !std::isfinite(d->vrot_max_kms))
+        return set_error(PZ_E_INVALID_ARG, "vrot_max_kms must be finite and >= 0");
+    if (!(d->limb_eps >= 0.0 && d->limb_eps <= 1.0))
+        return set_error(PZ_E_INVALID_ARG, "limb_eps must lie in [0, 1]");
+    // rotation support: the cells [k - 1/2, k + 1/2] that reach |u| <= s_max
+    const double JRd = d->vrot_max_kms > 0.0 ? std::ceil(d->vrot_max_kms / C_KMS / h + 0.5) : 0.0;
+    if (JRd > MAX_J) return set_error(PZ_E_INVALID_ARG, "vrot_max_kms gives a rotation support above 1024 pixels");
+    const int JR = (int)JRd;
     std::vector<int> lo(P), hi(P);
     std::vector<float> off(P), ap(P);
     for (int p = 0; p < P; ++p) {
@@ -336,7 +453,9 @@ int pz_inst_create(const pz_grid* grid, const pz_inst_desc* d, pz_inst** out) {
     const size_t o_lo = take(P * 4), o_hi = take(P * 4), o_off = take(P * 4), o_ap = take(P * 4),
                  o_plo = take((size_t)N * 4), o_phi = take((size_t)N * 4), o_BF = take((size_t)2 * N * 4),
                  o_Z = take((size_t)N * 4), o_KW = take(P * 4), o_dY = take((size_t)2 * P * 4),
-                 o_dS = take((size_t)2 * N * 4), o_dB = take((size_t)2 * N * 4), o_part = take((size_t)2 * nblk * 4);
+                 o_dS = take((size_t)2 * N * 4), o_dB = take((size_t)2 * N * 4), o_part = take((size_t)3 * nblk * 4),
+                 o_RBF = take(JR ? (size_t)2 * N * 4 : 0), o_ZR = take(JR ? (size_t)N * 4 : 0),
+                 o_dR = take(JR ? (size_t)2 * N * 4 : 0);
     pz_inst* in = new (std::nothrow) pz_inst();
     if (!in) return set_error(PZ_E_NOMEM, "host allocation failed");
     char* base = nullptr;
@@ -348,8 +467,10 @@ int pz_inst_create(const pz_grid* grid, const pz_inst_desc* d, pz_inst** out) {
     in->N = N;
     in->P = P;
     in->J = J;
+    in->JR = JR;
     in->nblk = nblk;
     in->h = h;
+    in->eps = d->limb_eps;
     in->base = base;
     in->lo = (int*)(base + o_lo);
     in->hi = (int*)(base + o_hi);
@@ -364,6 +485,9 @@ int pz_inst_create(const pz_grid* grid, const pz_inst_desc* d, pz_inst** out) {
     in->dS = (float*)(base + o_dS);
     in->dB = (float*)(base + o_dB);
     in->part = (float*)(base + o_part);
+    in->RBF = JR ? (float*)(base + o_RBF) : nullptr;
+    in->ZR = JR ? (float*)(base + o_ZR) : nullptr;
+    in->dR = JR ? (float*)(base + o_dR) : nullptr;
     hipError_t e = hipMemcpy(in->lo, lo.data(), P * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(in->hi, hi.data(), P * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(in->off, off.data(), P * 4, hipMemcpyHostToDevice);
@@ -391,10 +515,15 @@ int pz_inst_forward(const pz_inst* in, const float* F, const float* Fc, const fl
     if (!in || !F || !Fc || !vel) return set_error(PZ_E_INVALID_ARG, "inst, F, Fc and vel are required");
     if (!KF && !KFc && !f) return set_error(PZ_E_INVALID_ARG, "no output requested");
     hipStream_t st = (hipStream_t)stream;
+    const int gN = (in->N + TPB - 1) / TPB;
     const size_t lds = (size_t)(in->J + 1) * 4;
-    k_broaden<<<(in->N + TPB - 1) / TPB, TPB, lds, st>>>(in->N, in->J, in->h, vel, F, Fc, in->BF, in->Z);
-    k_lsf<<<(in->P + TPB - 1) / TPB, TPB, 0, st>>>(in->N, in->P, in->h, vel, in->lo, in->hi, in->off, in->ap, in->BF,
-                                                   KF, KFc, f, nullptr, nullptr, nullptr);
+    k_broaden<<<gN, TPB, lds, st>>>(in->N, in->J, in->h, vel, F, Fc, in->BF, in->Z);
+    if (in->JR)
+        k_rotate<<<gN, TPB, (size_t)2 * (in->JR + 1) * 4, st>>>(in->N, in->JR, in->h, in->eps, vel, in->BF, in->RBF,
+                                                                in->ZR);
+    const float* src = in->JR ? in->RBF : in->BF;
+    k_lsf<<<(in->P + TPB - 1) / TPB, TPB, 0, st>>>(in->N, in->P, in->h, vel, in->lo, in->hi, in->off, in->ap, src, KF,
+                                                   KFc, f, nullptr, nullptr, nullptr);
     INST_HIP(hipGetLastError());
     return PZ_OK;
 }
@@ -406,14 +535,20 @@ int pz_inst_backward(const pz_inst* in, const float* F, const float* Fc, const f
     hipStream_t st = (hipStream_t)stream;
     const int gN = (in->N + TPB - 1) / TPB;
     const size_t lds = (size_t)(in->J + 1) * 4;
+    const size_t ldsr = (size_t)2 * (in->JR + 1) * 4;
     k_broaden<<<gN, TPB, lds, st>>>(in->N, in->J, in->h, vel, F, Fc, in->BF, in->Z);
-    k_lsf<<<(in->P + TPB - 1) / TPB, TPB, 0, st>>>(in->N, in->P, in->h, vel, in->lo, in->hi, in->off, in->ap, in->BF,
+    if (in->JR) k_rotate<<<gN, TPB, ldsr, st>>>(in->N, in->JR, in->h, in->eps, vel, in->BF, in->RBF, in->ZR);
+    const float* src = in->JR ? in->RBF : in->BF;
+    k_lsf<<<(in->P + TPB - 1) / TPB, TPB, 0, st>>>(in->N, in->P, in->h, vel, in->lo, in->hi, in->off, in->ap, src,
                                                    nullptr, nullptr, nullptr, dL_df, in->KW, in->dY);
     k_lsf_T<<<gN, TPB, 0, st>>>(in->N, in->P, in->lo, in->off, in->ap, in->plo, in->phi, in->dY, in->dS);
-    k_shift_T<<<gN, TPB, 0, st>>>(in->N, in->h, vel, in->BF, in->dS, in->dB, in->part);
+    k_shift_T<<<gN, TPB, 0, st>>>(in->N, in->h, vel, src, in->dS, in->JR ? in->dR : in->dB, in->part);
+    if (in->JR)
+        k_rotate_T<<<gN, TPB, ldsr, st>>>(in->N, in->JR, in->h, in->eps, vel, in->BF, in->RBF, in->ZR, in->dR, in->dB,
+                                          in->part + 2 * in->nblk);
     k_broaden_T<<<gN, TPB, lds, st>>>(in->N, in->J, in->h, vel, F, Fc, in->Z, in->dB, dL_dF, dL_dFc,
                                       in->part + in->nblk);
-    if (g_vel) k_vel_final<<<1, TPB, 0, st>>>(in->nblk, in->h, vel, in->part, g_vel);
+    if (g_vel) k_vel_final<<<1, TPB, 0, st>>>(in->nblk, in->JR ? 1 : 0, in->h, vel, in->part, g_vel);
     INST_HIP(hipGetLastError());
     return PZ_OK;
 }

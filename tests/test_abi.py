@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(pz):
 
 
 def test_version(pz):
-    assert pz.pz_version() == pz.ABI_VERSION == 5
+    assert pz.pz_version() == pz.ABI_VERSION == 6
 
 
 def _lines(pz, L=3, **over):
@@ -128,7 +128,8 @@ def test_entry_points_reject_null_before_device_work(pz):
     assert pz.lib.pz_plan_info(None, None, None, None, None, None, None) == pz.PZ_E_INVALID_ARG
 
 
-@pytest.mark.parametrize("case", ["support_low", "support_high", "order", "sigma", "vbmax", "J", "P"])
+@pytest.mark.parametrize("case", ["support_low", "support_high", "order", "sigma", "vbmax", "J", "P", "vrot", "JR",
+                                  "eps"])
 def test_instrument_validation(pz, case):
     """pz_inst_create validates on the host before any device call."""
     import numpy as np
@@ -136,7 +137,7 @@ def test_instrument_validation(pz, case):
     h = np.log1p(1.0 / 3e5)
     lam = 1550.0 * np.exp(h * np.linspace(300, 900, 40))
     sig = np.full(40, 2e-5)
-    vb, P = 10.0, 40
+    vb, P, vrot, eps = 10.0, 40, 0.0, 0.6
     if case == "support_low":
         lam[0] = 1550.0 * np.exp(h * 3)
     elif case == "support_high":
@@ -151,8 +152,14 @@ def test_instrument_validation(pz, case):
         vb = 1e5
     elif case == "P":
         P = 0
+    elif case == "vrot":
+        vrot = -1.0
+    elif case == "JR":
+        vrot = 2e3
+    elif case == "eps":
+        vrot, eps = 10.0, 1.5
     dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
-    d = pz.pz_inst_desc(P, dp(lam), dp(sig), 0.0, vb)
+    d = pz.pz_inst_desc(P, dp(lam), dp(sig), 0.0, vb, vrot, eps)
     out = C.c_void_p()
     rc = pz.lib.pz_inst_create(C.byref(g), C.byref(d), C.byref(out))
     assert rc in (-1, -2) and out.value is None, (rc, pz.lib.pz_last_error())

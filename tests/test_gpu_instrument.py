@@ -131,3 +131,91 @@ def test_fit_step_through_the_instrument(gpu_lib):
     grad_close_cond(g[2], ref["g_abund"], ref["abs_abund"], name="abund")
     grad_close_cond(g[3], ref["g_xi"], ref["abs_xi"], name="xi")
     np.testing.assert_allclose(gv.cpu().numpy(), [gvr_o, gvb_o], rtol=2e-3)
+
+
+# ------------------------------------------------- rotational broadening R
+VROT_MAX = 40.0
+
+
+@pytest.fixture(scope="module")
+def rot_setup(setup):
+    pz, grid, _, _, F, Fc = setup
+    lam, sig, vbmax = W.apogee_instrument(grid)
+    inst = pz.Instrument(grid, lam, sig, vbmax, vrot_max_kms=VROT_MAX, limb_eps=0.6)
+    oinst = I.Instrument(grid, lam, sig, vbmax, vrot_max_kms=VROT_MAX, limb_eps=0.6)
+    assert inst.n_vel == 3 and oinst.JR == 41
+    return pz, grid, inst, oinst, F, Fc
+
+
+@pytest.mark.parametrize("vr,vb,vs", [(0.0, 5.0, 12.5), (23.7, 3.2, 39.0), (-8.0, 2.4, 0.3), (4.0, 1.0, 46.0)])
+def test_rotation_forward_vs_oracle(rot_setup, vr, vb, vs):
+    """K S R B on the GPU against the oracle: a broad and a near-maximal v sin i,
+    one narrower than a pixel (the identity), and one above the support (cut
+    and renormalised, as the oracle does)."""
+    pz, grid, inst, oinst, F, Fc = rot_setup
+    P = inst.P
+    KF, KFc, f = (torch.empty(P, device="cuda") for _ in range(3))
+    print("pz_inst_forward rotation", vr, vb, vs, flush=True)
+    pz.pz_inst_forward(inst, _dev(F), _dev(Fc), _dev([vr, vb, vs]), KF, KFc, f)
+    torch.cuda.synchronize()
+    rKF, rKFc, rf = I.forward(oinst, F.astype(np.float64), Fc.astype(np.float64), vr, vb, vsini=vs)
+    for got, ref in ((KF, rKF), (KFc, rKFc), (f, rf)):
+        np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=1e-5)
+
+
+def test_rotation_zero_is_the_plain_operator(rot_setup, setup):
+    """v sin i = 0 gives r_0 = 1 and nothing else: bit-for-bit the instrument
+    without a rotation stage, forward and backward (v sin i gradient zero)."""
+    pz, grid, inst, _, F, Fc = rot_setup
+    plain = setup[2]
+    seed = _dev(np.random.default_rng(8).normal(size=inst.P))
+    outs = []
+    for ins, vel in ((plain, [6.0, 3.0]), (inst, [6.0, 3.0, 0.0])):
+        f = torch.empty(ins.P, device="cuda")
+        dF, dFc = torch.empty(grid.N, device="cuda"), torch.empty(grid.N, device="cuda")
+        gv = torch.full((3,), np.nan, device="cuda")
+        pz.pz_inst_forward(ins, _dev(F), _dev(Fc), _dev(vel), None, None, f)
+        pz.pz_inst_backward(ins, _dev(F), _dev(Fc), _dev(vel), seed, dF, dFc, gv)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (f, dF, dFc, gv)])
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(outs[0][3][:2], outs[1][3][:2])
+    assert outs[1][3][2] == 0.0
+
+
+@pytest.mark.parametrize("vr,vb,vs", [(12.0, 6.0, 18.0), (-30.0, 3.0, 33.0)])
+def test_rotation_backward_vs_oracle(rot_setup, vr, vb, vs):
+    """The VJP through R: dL/dF, dL/dFc to 1e-4 of their largest magnitude and
+    (dL/dv_r, dL/dv_b, dL/d v sin i) to 1e-3 relative, for a chi^2 seed
+    against a model at other velocities and another v sin i."""
+    pz, grid, inst, oinst, F, Fc = rot_setup
+    F64, Fc64 = F.astype(np.float64), Fc.astype(np.float64)
+    _, _, ymodel = I.forward(oinst, F64, Fc64, vr + 1.5, vb + 0.8, vsini=vs + 2.5)
+    _, _, f = I.forward(oinst, F64, Fc64, vr, vb, vsini=vs)
+    seed = (2.0 * (f - ymodel) / 1e-4).astype(np.float32)
+    dF, dFc = torch.empty(grid.N, device="cuda"), torch.empty(grid.N, device="cuda")
+    gv = torch.full((3,), np.nan, device="cuda")
+    print("pz_inst_backward rotation", vr, vb, vs, flush=True)
+    pz.pz_inst_backward(inst, _dev(F), _dev(Fc), _dev([vr, vb, vs]), _dev(seed), dF, dFc, gv)
+    torch.cuda.synchronize()
+    rdF, rdFc, rvr, rvb, rvs = I.adjoint(oinst, F64, Fc64, vr, vb, seed.astype(np.float64), vsini=vs)
+    for got, ref in ((dF, rdF), (dFc, rdFc)):
+        got = got.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+    g = gv.cpu().numpy()
+    print("g_vel", g, "oracle", [rvr, rvb, rvs], flush=True)
+    np.testing.assert_allclose(g, [rvr, rvb, rvs], rtol=1e-3)
+
+
+def test_rotation_backward_deterministic(rot_setup):
+    pz, grid, inst, oinst, F, Fc = rot_setup
+    seed = _dev(np.random.default_rng(5).normal(size=inst.P))
+    outs = []
+    for _ in range(2):
+        dF, dFc, gv = torch.empty(grid.N, device="cuda"), torch.empty(grid.N, device="cuda"), torch.empty(3, device="cuda")
+        pz.pz_inst_backward(inst, _dev(F), _dev(Fc), _dev([5.0, 4.0, 21.0]), seed, dF, dFc, gv)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (dF, dFc, gv)])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
