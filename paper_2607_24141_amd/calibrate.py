@@ -16,7 +16,8 @@ The objective is sum_s c_s sum_p w_sp (f_sp - y_sp)^2 over the standards s
 (each star's epochs share its synthesis).  The optimiser is L-BFGS with a
 strong-Wolfe line search over unconstrained u, with the smooth bound
 transform theta = b tanh(u / b) per correction kind; its vectors stay on the
-device and each evaluation costs one host transfer of two scalars.
+device, each evaluation costs one host transfer of two scalars and each
+iteration one more of the inner products with the stored pairs.
 """
 from __future__ import annotations
 
@@ -212,61 +213,120 @@ def _strong_wolfe(phi, f0, d0, t, c1=1e-4, c2=0.9, max_ls=25):
     return best
 
 
+class _Pairs:
+    """Curvature pairs (s_i, y_i) of L-BFGS in one device buffer B of 2 (m+1) + 1
+    rows of n: rows [0, m] hold s, rows [m+1, 2m+1] the matching y (slot k: rows k and
+    m+1+k), and the last
+    row the current gradient (m+1 slots, so a new pair never evicts an old one
+    before it is accepted).  The inner products that the compact form needs are
+    kept on the host in float64: R[i][j] = s_i.y_j and YY[i][j] = y_i.y_j by slot."""
+
+    def __init__(self, m, n, like):
+        self.m, self.M = m, m + 1
+        self.B = torch.zeros(2 * self.M + 1, n, dtype=like.dtype, device=like.device)
+        self.SY = np.zeros((self.M, self.M))
+        self.YY = np.zeros((self.M, self.M))
+        self.order = []                              # accepted slots, oldest first
+        self.gamma = 1.0
+
+    def free_slot(self):
+        return next(k for k in range(self.M) if k not in self.order)
+
+    def reset(self):
+        self.order = []
+        self.gamma = 1.0
+
+
+def _compact_direction(P, a, b, gg):
+    """d = -H g from the compact representation of the L-BFGS inverse Hessian
+    (Byrd, Nocedal and Schnabel 1994; Nocedal and Wright eq. 7.24),
+        H = gamma I + [S  gamma Y] [[R^-T (D + gamma Y^T Y) R^-1, -R^-T], [-R^-1, 0]] [S  gamma Y]^T,
+    R the upper triangle of S^T Y (pairs oldest first), D its diagonal: the
+    same H g as the two-loop recursion with H_0 = gamma I.  a = S^T g, b =
+    Y^T g by slot.  Returns the coefficients c of d = B^T c and g.d."""
+    o = P.order
+    c = np.zeros(2 * P.M + 1)
+    c[2 * P.M] = -P.gamma
+    if not o:
+        return c, -gg
+    idx = np.array(o)
+    R = np.triu(P.SY[np.ix_(idx, idx)])
+    Dg = np.diag(np.diag(R))
+    av, bv = a[idx], b[idx]
+    u = np.linalg.solve(R, av)                                      # R^-1 S^T g
+    q = -u
+    pv = np.linalg.solve(R.T, (Dg + P.gamma * P.YY[np.ix_(idx, idx)]) @ u - P.gamma * bv)
+    c[idx] = -pv
+    c[P.M + idx] = -P.gamma * q
+    gd = -P.gamma * gg - av @ pv - P.gamma * (bv @ q)
+    return c, gd
+
+
 def lbfgs(fg, x0, max_iter=40, history_size=10, max_eval=None):
-    """Limited-memory BFGS with a strong-Wolfe line search (Nocedal and Wright,
-    Algorithm 7.4 for the two-loop recursion).  fg(x) -> (f [1], g) on the
-    device; the direction, the curvature pairs and every vector update stay on
-    the device, and each evaluation costs one host transfer (f and the slope
-    along the direction, read together).  Returns dict(x, f, iters, evals,
-    history)."""
+    """Limited-memory BFGS with a strong-Wolfe line search.  fg(x) -> (f [1], g)
+    on the device.  The direction comes from the compact representation of the
+    inverse Hessian (equal to the two-loop recursion of Nocedal and Wright,
+    Algorithm 7.4): two matrix-vector products give every inner product with
+    the stored pairs, a host solve of at most m x m, and one more product forms
+    the direction.  Each iteration costs one host transfer for those inner
+    products and one per evaluation (f and the slope along the direction, read
+    together).  Returns dict(x, f, iters, evals, history)."""
     max_eval = max_eval or 4 * max_iter
     x = x0.detach().clone()
+    shape = x.shape
     f_t, g = fg(x)
     f = float(f_t[0])
     evals, hist = 1, [f]
-    S, Y, R = [], [], []                          # curvature pairs and 1/(y.s), device
+    n = x.numel()
+    P = _Pairs(history_size, n, x)
+    M = P.M
+    B = P.B
+    prods = torch.empty(2, 2 * M + 1, dtype=x.dtype, device=x.device)
+    new_slot = None                                  # pair written by the last iteration, not yet tested
     it = 0
     while it < max_iter and evals < max_eval:
-        # two-loop recursion for d = -H g
-        q = -g
-        alpha = []
-        for s_i, y_i, r_i in zip(reversed(S), reversed(Y), reversed(R)):
-            a_i = r_i * torch.dot(s_i.flatten(), q.flatten())
-            q = q - a_i * y_i
-            alpha.append(a_i)
-        if S:
-            q = q * (torch.dot(S[-1].flatten(), Y[-1].flatten()) / torch.dot(Y[-1].flatten(), Y[-1].flatten()))
-        for (s_i, y_i, r_i), a_i in zip(zip(S, Y, R), reversed(alpha)):
-            b_i = r_i * torch.dot(y_i.flatten(), q.flatten())
-            q = q + (a_i - b_i) * s_i
-        d = q
-        gd_t = torch.dot(g.flatten(), d.flatten())
-        gd = float(gd_t)
+        B[2 * M].copy_(g.reshape(-1))
+        torch.mv(B, g.reshape(-1), out=prods[0])
+        if new_slot is not None:
+            torch.mv(B, B[M + new_slot], out=prods[1])
+        v = prods.cpu().double().numpy()
+        a, b, gg = v[0, :M], v[0, M:2 * M], float(v[0, 2 * M])
+        if new_slot is not None:
+            k = new_slot
+            sy, yy = v[1, :M], v[1, M:2 * M]               # s_i.y_k and y_i.y_k by slot
+            ys = float(sy[k])
+            if ys > 1e-10:
+                P.SY[:, k] = sy
+                P.YY[:, k] = yy
+                P.YY[k, :] = yy
+                P.order.append(k)
+                if len(P.order) > P.m:
+                    P.order.pop(0)
+                P.gamma = ys / float(yy[k])
+            new_slot = None
+        c, gd = _compact_direction(P, a, b, gg)
+        d = torch.mv(B.t(), torch.as_tensor(c, dtype=x.dtype).to(x.device, non_blocking=False)).reshape(shape)
         if not gd < 0.0:                          # not a descent direction: restart from -g
-            S, Y, R = [], [], []
+            P.reset()
             d = -g
-            gd = float(torch.dot(g.flatten(), d.flatten()))
+            gd = -gg
             if gd == 0.0:
                 break
         t0 = min(1.0, 1.0 / float(g.abs().sum())) if it == 0 else 1.0
 
         def phi(t):
             nonlocal evals
-            xt = x + t * d
+            xt = torch.add(x, d, alpha=t)
             ft, gt = fg(xt)
             evals += 1
-            v = torch.stack([ft[0], torch.dot(gt.flatten(), d.flatten())]).tolist()
-            return v[0], v[1], (xt, gt)
+            w = torch.stack([ft.reshape(-1)[0], torch.dot(gt.flatten(), d.flatten())]).tolist()
+            return w[0], w[1], (xt, gt)
 
         t, f_new, (x_new, g_new) = _strong_wolfe(phi, f, gd, t0, max_ls=max(1, min(25, max_eval - evals)))
-        s_k, y_k = x_new - x, g_new - g
-        ys = torch.dot(y_k.flatten(), s_k.flatten())
-        if float(ys) > 1e-10:
-            if len(S) == history_size:
-                S.pop(0), Y.pop(0), R.pop(0)
-            S.append(s_k)
-            Y.append(y_k)
-            R.append(1.0 / ys)
+        k = P.free_slot()
+        torch.sub(x_new.reshape(-1), x.reshape(-1), out=B[k])
+        torch.sub(g_new.reshape(-1), g.reshape(-1), out=B[M + k])
+        new_slot = k
         x, g, f = x_new, g_new, f_new
         hist.append(f)
         it += 1

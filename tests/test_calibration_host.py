@@ -153,3 +153,51 @@ def test_lbfgs_quadratic_and_wolfe():
     d0 = float(torch.dot(g0, d))
     assert f <= float(f0) + 1e-4 * t * d0
     assert abs(float(torch.dot(fg(t * d)[1], d))) <= 0.9 * abs(d0)
+
+
+def test_lbfgs_compact_direction_is_the_two_loop_recursion():
+    """The compact representation of the inverse Hessian gives the same
+    direction as the two-loop recursion (Nocedal and Wright, Algorithm 7.4)
+    for the same pairs and H_0 = gamma I, gamma = s.y / y.y of the newest
+    pair; pairs stored in a ring of slots in any order."""
+    import torch
+    CAL = _lbfgs()
+    rng = np.random.default_rng(9)
+    n, m = 60, 5
+    A = rng.normal(size=(n, n))
+    Hs = A @ A.T + n * np.eye(n)                     # SPD: every pair has s.y > 0
+    P = CAL._Pairs(m, n, torch.zeros(n, dtype=torch.float64))
+    pairs = []
+    for step in range(8):                            # more pairs than the history holds
+        s = rng.normal(size=n)
+        y = Hs @ s
+        k = P.free_slot()
+        P.B[k] = torch.as_tensor(s)
+        P.B[P.M + k] = torch.as_tensor(y)
+        B = P.B.numpy()
+        P.SY[:, k] = B[:P.M] @ y
+        P.YY[:, k] = B[P.M:2 * P.M] @ y
+        P.YY[k, :] = P.YY[:, k]
+        P.order.append(k)
+        if len(P.order) > m:
+            P.order.pop(0)
+        P.gamma = (s @ y) / (y @ y)
+        pairs = (pairs + [(s, y)])[-m:]
+        g = rng.normal(size=n)
+        P.B[2 * P.M] = torch.as_tensor(g)
+        B = P.B.numpy()
+        c, gd = CAL._compact_direction(P, B[:P.M] @ g, B[P.M:2 * P.M] @ g, g @ g)
+        d = B.T @ c
+        # the two-loop recursion
+        q = g.copy()
+        al = []
+        for s_i, y_i in reversed(pairs):
+            a_i = (s_i @ q) / (y_i @ s_i)
+            q -= a_i * y_i
+            al.append(a_i)
+        r = q * P.gamma
+        for (s_i, y_i), a_i in zip(pairs, reversed(al)):
+            b_i = (y_i @ r) / (y_i @ s_i)
+            r += (a_i - b_i) * s_i
+        np.testing.assert_allclose(d, -r, rtol=1e-9, atol=1e-12 * np.abs(r).max())
+        assert abs(gd - g @ d) <= 1e-9 * abs(gd)
