@@ -93,8 +93,9 @@ __global__ __launch_bounds__(512) void kb_params(const StarDev* __restrict__ sta
 }
 
 // ANYCT: some star of the batch uses the centre test (the LDS holds its rows);
-// G: depth-group slots (at least D / (64 / WPX) for every star).
-template <int WPX, bool ANYCT, int G>
+// G: depth-group slots (at least D / (64 / WPX) for every star); FG: exactly
+// D / (64 / WPX) for every star.
+template <int WPX, bool ANYCT, int G, bool FG>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     PZ_OPACITY_LDS(WPX, ANYCT, sm);
     __shared__ int s_it;
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void kb_opacity(const St
         if (it >= n) return;
         const int2 w = uniform_item(items, it);
         const StarDev& s = stars[w.x];
-        dev_opacity_tile<WPX, false, ANYCT, G, false>(s, w.y, s.chunk, sm);
+        dev_opacity_tile<WPX, false, ANYCT, G, false, FG>(s, w.y, s.chunk, sm);
     }
 }
 
@@ -227,9 +228,9 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <bool ANYCT>
 static hipError_t batch_opacity_occupancy(int* occ) {
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], kb_opacity<4, ANYCT, 4>, 512, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], kb_opacity<8, ANYCT, 9>, 512, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], kb_opacity<16, ANYCT, 19>, 512, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], kb_opacity<4, ANYCT, 4, true>, 512, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], kb_opacity<8, ANYCT, 9, true>, 512, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], kb_opacity<16, ANYCT, 19, false>, 512, 0);
     return e;
 }
 
@@ -239,6 +240,7 @@ struct pz_batch {
     bool has_target;
     bool any_center;      // some star uses the centre test
     int max_d;            // largest depth count of the stars
+    int min_d;            // smallest depth count of the stars
     std::vector<const pz_plan*> plans;
     int n_items[N_PHASE];
     int2* items[N_PHASE];
@@ -252,14 +254,20 @@ struct pz_batch {
 };
 
 // One phase's opacity launches: the main pass with the fewest depth-group
-// slots that hold every star's D / (64 / WPX) groups, then the wide pass.
+// slots that hold every star's D / (64 / WPX) groups (with no empty slot when
+// every star has the same group count), then the wide pass.
 template <int WPX, bool ANYCT>
 static void batch_opacity_wpx(const pz_batch* bt, int n, const int2* items, int* ctr, int grid, hipStream_t st) {
     constexpr int GB = opacity_max_groups<WPX>();
-    if (bt->max_d / (64 / WPX) < GB)
-        kb_opacity<WPX, ANYCT, GB - 1><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
+    const int ng = bt->max_d / (64 / WPX);             // <= GB: D <= MAXD
+    const bool same = bt->min_d / (64 / WPX) == ng;
+    if (ng == GB)
+        same ? kb_opacity<WPX, ANYCT, GB, true><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr)
+             : kb_opacity<WPX, ANYCT, GB, false><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
+    else if (ng == GB - 1 && same)
+        kb_opacity<WPX, ANYCT, GB - 1, true><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
     else
-        kb_opacity<WPX, ANYCT, GB><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
+        kb_opacity<WPX, ANYCT, GB - 1, false><<<grid, 512, 0, st>>>(bt->stars, items, n, ctr);
     kb_opacity_wide<WPX, ANYCT><<<grid, 512, 0, st>>>(bt->stars, items, n);
 }
 
@@ -379,9 +387,11 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, bt->device);
     bt->any_center = false;
     bt->max_d = 0;
+    bt->min_d = MAXD;
     for (int b = 0; b < n_star; ++b) {
         bt->any_center = bt->any_center || sd[b].center;
         bt->max_d = std::max(bt->max_d, sd[b].D);
+        bt->min_d = std::min(bt->min_d, sd[b].D);
     }
     if (e == hipSuccess)
         e = bt->any_center ? batch_opacity_occupancy<true>(occ_op) : batch_opacity_occupancy<false>(occ_op);

@@ -28,8 +28,8 @@ __global__ __launch_bounds__(256) void k_line_params(StarDev s) {
 // (band clusters), and a one-shot grid of ~N/TPX workgroups leaves a long
 // tail of heavy tiles.
 // CT: the plan uses the centre test (its LDS holds the zmax rows); G: depth-group
-// slots per lane (at least D / (64 / WPX)).
-template <int WPX, bool CT, int G>
+// slots per lane (at least D / (64 / WPX)); FG: exactly D / (64 / WPX).
+template <int WPX, bool CT, int G, bool FG>
 __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s, int chunk) {
     PZ_OPACITY_LDS(WPX, CT, sm);
     __shared__ int s_it;
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(512) PZ_OPACITY_WAVES(WPX) void k_opacity(StarDev s
         const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= s.n_tiles) return;
-        dev_opacity_tile<WPX, false, CT, G, true>(s, s.tile_order[it], chunk, sm);
+        dev_opacity_tile<WPX, false, CT, G, true, FG>(s, s.tile_order[it], chunk, sm);
     }
 }
 
@@ -65,9 +65,9 @@ __global__ __launch_bounds__(256) void k_select(StarDev s, double eta, double bi
 template <bool CT>
 static hipError_t opacity_occupancy(int tile_px, int* occ) {
     switch (tile_px) {
-        case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<4, CT, 4>, 512, 0);
-        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<8, CT, 9>, 512, 0);
-        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<16, CT, 19>, 512, 0);
+        case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<4, CT, 4, true>, 512, 0);
+        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<8, CT, 9, true>, 512, 0);
+        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_opacity<16, CT, 19, false>, 512, 0);
     }
 }
 
@@ -221,14 +221,17 @@ hipError_t launch_line_params(const StarDev& s, hipStream_t st) {
 }
 
 // The main pass with the fewest depth-group slots that hold D / (64 / WPX)
-// groups, then the wide pass.
+// groups (with no empty slot where the depths allow), then the wide pass.
 template <int WPX, bool CT>
 static void launch_opacity_wpx(const StarDev& s, int chunk, int grid, hipStream_t st) {
     constexpr int GB = opacity_max_groups<WPX>();
-    if (s.D / (64 / WPX) < GB)
-        k_opacity<WPX, CT, GB - 1><<<grid, 512, 0, st>>>(s, chunk);
+    const int ng = s.D / (64 / WPX);                   // <= GB: D <= MAXD
+    if (ng == GB)
+        k_opacity<WPX, CT, GB, true><<<grid, 512, 0, st>>>(s, chunk);
+    else if (ng == GB - 1)
+        k_opacity<WPX, CT, GB - 1, true><<<grid, 512, 0, st>>>(s, chunk);
     else
-        k_opacity<WPX, CT, GB><<<grid, 512, 0, st>>>(s, chunk);
+        k_opacity<WPX, CT, GB - 1, false><<<grid, 512, 0, st>>>(s, chunk);
     k_opacity_wide<WPX, CT><<<grid, 512, 0, st>>>(s, chunk);
 }
 

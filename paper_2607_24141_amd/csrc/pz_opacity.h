@@ -244,7 +244,7 @@ __device__ __forceinline__ void wing_sums(float* acc, const float4* pd, const fl
 template <int WPX>
 constexpr int opacity_max_groups() { return MAXD / (64 / WPX); }
 
-template <int WPX, bool CT, bool WIDE, int G, bool PAIRED, class Lds>
+template <int WPX, bool CT, bool WIDE, int G, bool PAIRED, bool FG, class Lds>
 __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, int chunk, const Lds& sm) {
     constexpr int NDG = 64 / WPX;
     constexpr int DPT = G;                             // depth-group slots (>= full groups)
@@ -256,7 +256,9 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
     const int px = wave * WPX + lane % WPX;           // main pixel within the tile
     const int dg = lane / WPX;
     const int D = s.D;
-    const int nfull = D / NDG, r = D - nfull * NDG;
+    // FG: every slot holds a full group (D / NDG == G, checked at launch), so
+    // the per-group guards below fold away and the groups' sums interleave
+    const int nfull = FG ? G : D / NDG, r = D - nfull * NDG;
     const int t = tid;                                 // tail slot
     const bool tail = t < TPX * r;
     const int tpx = tail ? t / r : 0;
@@ -406,16 +408,16 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 // far wing tiers across depths) with the evaluator that keeps each lane on
 // its own tier.  ANYCT: the workgroup's LDS has the centre test's rows, so
 // stars with the centre test are taken too.
-// G: depth-group slots, at least the star's D / NDG.  PAIRED: the plain sum
-// runs its chunks in statically paired buffers (faster where the registers
-// allow, as in the single-star kernels; the batch kernels, which also hold
-// their work queue's state, take the one-body loop).
-template <int WPX, bool WIDE, bool ANYCT, int G, bool PAIRED>
+// G: depth-group slots, at least the star's D / NDG; FG: exactly D / NDG.
+// PAIRED: the plain sum runs its chunks in statically paired buffers (faster
+// where the registers allow, as in the single-star kernels; the batch
+// kernels, which also hold their work queue's state, take the one-body loop).
+template <int WPX, bool WIDE, bool ANYCT, int G, bool PAIRED, bool FG = false>
 __device__ __forceinline__ void dev_opacity_tile(const StarDev& s, int tile, int chunk, const OpacityLds<WPX, ANYCT>& sm) {
     if (ANYCT && s.center)
-        opacity_tile_body<WPX, ANYCT, WIDE, G, PAIRED>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, ANYCT, WIDE, G, PAIRED, FG>(s, tile, chunk, sm);
     else
-        opacity_tile_body<WPX, false, WIDE, G, PAIRED>(s, tile, chunk, sm);
+        opacity_tile_body<WPX, false, WIDE, G, PAIRED, FG>(s, tile, chunk, sm);
 }
 
 }  // namespace pz

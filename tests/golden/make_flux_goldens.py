@@ -11,6 +11,10 @@ FP64 oracle (Sec. 2.1 Eqs. 1-9; the plain windowed sum, Gauss-3 in mu):
                                 float64 [n].  A pixel's flux depends only on the
                                 lines within W of it, so a slice of the oracle is
                                 exactly that part of the whole spectrum.
+  flux_batch_stars_golden.npz   every pixel of three stars of the 256-star
+                                batch (stars 0, 101 and 255: their own
+                                atmospheres, windows and catalogues):
+                                F_<b>, Fc_<b> float64 [N_b]
 
 Calls only oracle/ and workloads/ (seeded generators).
 
@@ -31,13 +35,19 @@ import workloads as W  # noqa: E402
 from oracle import synth as O  # noqa: E402
 
 WL = None
+BATCH_STARS = (0, 101, 255)
 SLICE_STARTS_NM = (300.0, 650.0, None)   # None: the slice that ends at the last pixel
 SLICE_NM = 2.0
 
 
 def _init(name):
     global WL
-    WL = W.giant_1500_1700nm() if name == "1500_1700" else W.solar_300_1000nm()
+    if name == "1500_1700":
+        WL = W.giant_1500_1700nm()
+    elif name == "300_1000":
+        WL = W.solar_300_1000nm()
+    else:
+        WL = W.batch_star(int(name.split("_")[1]))
 
 
 def _fwd(pix):
@@ -69,7 +79,7 @@ def run(name, pix, procs, chunk):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--procs", type=int, default=8)
-    ap.add_argument("--only", choices=["1500_1700", "300_1000"], default=None)
+    ap.add_argument("--only", choices=["1500_1700", "300_1000", "batch"], default=None)
     args = ap.parse_args()
     if args.only in (None, "1500_1700"):
         t0 = time.time()
@@ -86,6 +96,15 @@ def main():
         np.savez_compressed(os.path.join(HERE, "flux_300_1000nm_slices_golden.npz"), pix=pix, F=F, Fc=Fc,
                             workload=wl.name)
         print("300-1000 nm slices: %d pixels, %.0f s" % (F.size, time.time() - t0), flush=True)
+    if args.only in (None, "batch"):
+        t0 = time.time()
+        out = {}
+        for b in BATCH_STARS:
+            wl = W.batch_star(b)
+            F, Fc = run("star_%d" % b, np.arange(wl.grid.N, dtype=np.int64), args.procs, 256)
+            out["F_%d" % b], out["Fc_%d" % b] = F, Fc
+        np.savez_compressed(os.path.join(HERE, "flux_batch_stars_golden.npz"), stars=np.array(BATCH_STARS), **out)
+        print("batch stars %s: %.0f s" % (BATCH_STARS, time.time() - t0), flush=True)
 
 
 if __name__ == "__main__":

@@ -71,6 +71,7 @@ def test_target_and_seed_reproduce(golden):
 # and the slices are the 2-nm pieces they claim to be.
 FLUX_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "flux_1500_1700nm_golden.npz")
 SLICE_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "flux_300_1000nm_slices_golden.npz")
+BATCH_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "flux_batch_stars_golden.npz")
 
 
 def test_flux_golden_1500_1700nm_reproduces():
@@ -83,6 +84,22 @@ def test_flux_golden_1500_1700nm_reproduces():
     np.testing.assert_allclose(z["F"][pix], F, rtol=1e-12)
     np.testing.assert_allclose(z["Fc"][pix], Fc, rtol=1e-12)
     assert np.all(z["F"] > 0) and np.all(z["F"] <= z["Fc"])
+
+
+def test_flux_golden_batch_stars_reproduce():
+    """Every pixel of three batch stars (own atmosphere, window and catalogue):
+    sampled pixels of each recomputed by the oracle."""
+    z = np.load(BATCH_GOLDEN)
+    rng = np.random.default_rng(8)
+    for b in z["stars"]:
+        wl = W.batch_star(int(b))
+        F = z["F_%d" % b]
+        assert F.shape == (wl.grid.N,)
+        pix = np.unique(np.concatenate([[0, wl.grid.N - 1], rng.integers(0, wl.grid.N, 3)]))
+        Fo, Fco = O.synthesize(wl, pix=pix)
+        np.testing.assert_allclose(F[pix], Fo, rtol=1e-12)
+        np.testing.assert_allclose(z["Fc_%d" % b][pix], Fco, rtol=1e-12)
+        assert np.all(F > 0) and np.all(F <= z["Fc_%d" % b])
 
 
 def test_flux_golden_300_1000nm_slices():

@@ -189,3 +189,25 @@ def test_autotune_returns_supported_config(gpu_lib):
     tile, chunk, ms = pz.pz_autotune(wl.grid, wl.lines, wl.atm.S, wl.atm.D, pz.Atmos(wl.atm),
                                      pz.Params.from_host(wl.params), reps=2)
     assert tile in (32, 64, 128) and chunk in (8, 16) and ms > 0
+
+
+def test_batch_stars_every_pixel_vs_golden(gpu_lib):
+    """Three stars of the batch (stars 0, 101 and 255) in one synth_batch
+    call: every pixel of F, F_c and f against the oracle's full spectra
+    (tests/golden/flux_batch_stars_golden.npz) at 1e-4."""
+    import os
+    pz = gpu_lib
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "flux_batch_stars_golden.npz"))
+    ids = [int(b) for b in z["stars"]]
+    stars = [Star(pz, W.batch_star(b), seed=b) for b in ids]
+    batch = pz.Batch([s.descr(pz) for s in stars])
+    print("synth_batch stars", ids, [s.plan.N for s in stars], flush=True)
+    pz.synth_batch(batch, pz.PZ_MODE_FWD)
+    torch.cuda.synchronize()
+    for b, s in zip(ids, stars):
+        F, Fc = s.F.cpu().numpy().astype(np.float64), s.Fc.cpu().numpy().astype(np.float64)
+        Fo, Fco = z["F_%d" % b], z["Fc_%d" % b]
+        errs = [np.max(np.abs(got - ref) / ref) for got, ref in ((F, Fo), (Fc, Fco), (F / Fc, Fo / Fco))]
+        print("star", b, "max rel err F, Fc, f", errs, flush=True)
+        assert max(errs) <= 1e-4
+    batch.destroy()
