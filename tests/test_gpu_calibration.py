@@ -115,8 +115,10 @@ EPS_F = 1e-5     # float32 model error in f, the bound of the forward and instru
 
 def test_objective_and_gradient_vs_oracle(gpu_lib):
     """Two stars (a dwarf and a giant observed at two epochs) share 46 lines;
-    loss to 1e-4 relative; group gradients to 2e-3 relative plus 1e-5 of the
-    sum of absolute contributions, plus the propagated float32 model error
+    loss to 1e-4 relative; group gradients to the 1e-3 rule (1e-3 relative
+    where |g| >= 1e-2 max, else 1e-5 max) or, for ill-conditioned groups only,
+    1e-3 relative plus 1e-5 of the sum of absolute contributions plus the
+    propagated float32 model error
     EPS_F (the seed 2 c w (f - y) carries it where f - y is small, and a weak
     group's gradient is a sum of noise residuals of either sign)."""
     from paper_2607_24141_amd import calibrate as CAL
@@ -145,11 +147,11 @@ def test_objective_and_gradient_vs_oracle(gpu_lib):
     unit = _unit_residual_scale(stds, q, G, theta32.astype(np.float64))
     from test_gpu_adjoint import TERM_TOL
     for r, kind in enumerate(CAL.KINDS):
-        grad_close_cond(g[r], ref_g[r], ref_abs[r] + EPS_F / TERM_TOL * unit[r], rtol=2e-3, name=kind,
+        grad_close_cond(g[r], ref_g[r], ref_abs[r] + EPS_F / TERM_TOL * unit[r], rtol=1e-3, name=kind,
                         cond_fallback=True)
-    # strong groups (the 25 % largest gradients) hold to 2e-3 relative alone
+    # strong groups (the 25 % largest gradients) hold to 1e-3 relative alone
     big = np.abs(ref_g) >= np.quantile(np.abs(ref_g), 0.75)
-    assert np.all(np.abs(g - ref_g)[big] <= 2e-3 * np.abs(ref_g)[big])
+    assert np.all(np.abs(g - ref_g)[big] <= 1e-3 * np.abs(ref_g)[big])
     # the autograd wrapper returns the same value and gradient
     t = _dev(theta32).requires_grad_(True)
     val = CAL.loss_fn(gc, t)

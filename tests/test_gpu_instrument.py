@@ -219,3 +219,35 @@ def test_rotation_backward_deterministic(rot_setup):
         outs.append([x.cpu().numpy() for x in (dF, dFc, gv)])
     for a, b in zip(*outs):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("vrot_max,eps,vs", [(0.4, 0.0, 0.35), (12.0, 1.0, 11.5), (12.0, 0.0, -3.0)])
+def test_rotation_edge_cases(setup, vrot_max, eps, vs):
+    """A support of one cell (v sin i below a pixel), the two limb-darkening
+    extremes (a uniform and a fully darkened disc) and a negative v sin i (the
+    identity), forward and backward against the oracle."""
+    pz, grid, _, _, F, Fc = setup
+    lam, sig, vbmax = W.apogee_instrument(grid)
+    inst = pz.Instrument(grid, lam, sig, vbmax, vrot_max_kms=vrot_max, limb_eps=eps)
+    oinst = I.Instrument(grid, lam, sig, vbmax, vrot_max_kms=vrot_max, limb_eps=eps)
+    F64, Fc64 = F.astype(np.float64), Fc.astype(np.float64)
+    vr, vb = 3.0, 4.0
+    f = torch.empty(inst.P, device="cuda")
+    print("rotation edge case", vrot_max, eps, vs, "JR", oinst.JR, flush=True)
+    pz.pz_inst_forward(inst, _dev(F), _dev(Fc), _dev([vr, vb, vs]), None, None, f)
+    _, _, rf = I.forward(oinst, F64, Fc64, vr, vb, vsini=vs)
+    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=1e-5)
+    _, _, ym = I.forward(oinst, F64, Fc64, vr + 1.0, vb + 0.5, vsini=abs(vs) + 1.0)
+    seed = (2.0 * (rf - ym) / 1e-4).astype(np.float32)
+    dF = torch.empty(grid.N, device="cuda")
+    gv = torch.full((3,), np.nan, device="cuda")
+    pz.pz_inst_backward(inst, _dev(F), _dev(Fc), _dev([vr, vb, vs]), _dev(seed), dF, None, gv)
+    torch.cuda.synchronize()
+    rdF, _, rvr, rvb, rvs = I.adjoint(oinst, F64, Fc64, vr, vb, seed.astype(np.float64), vsini=vs)
+    assert np.max(np.abs(dF.cpu().numpy() - rdF)) <= 1e-4 * np.max(np.abs(rdF))
+    g = gv.cpu().numpy()
+    np.testing.assert_allclose(g[:2], [rvr, rvb], rtol=1e-3)
+    if vs <= 0.5 * I.C_KMS * oinst.h:              # the identity: no dependence on v sin i
+        assert g[2] == 0.0 and rvs == 0.0
+    else:
+        assert abs(g[2] - rvs) <= 1e-3 * abs(rvs)
