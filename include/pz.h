@@ -330,9 +330,10 @@ typedef struct {
  * synth_batch be a pure enqueue that can be captured and replayed.  The
  * per-star plans and every buffer a star names must outlive the batch, and no
  * two stars may share a plan (each plan's workspace holds that star's
- * intermediate arrays).  Synchronises the device.  Errors: PZ_E_INVALID_ARG
- * (null arguments, shared plans, a scattering atmosphere: PZ_E_UNSUPPORTED),
- * the per-star checks of synth_forward, PZ_E_NOMEM, PZ_E_HIP. */
+ * intermediate arrays).  A star whose atmosphere has continuum scattering
+ * needs a plan built with PZ_FLAG_SCATTERING, as for synth_forward.
+ * Synchronises the device.  Errors: PZ_E_INVALID_ARG (null arguments, shared
+ * plans), the per-star checks of synth_forward, PZ_E_NOMEM, PZ_E_HIP. */
 int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out);
 void pz_batch_destroy(pz_batch* batch);
 
@@ -340,7 +341,9 @@ void pz_batch_destroy(pz_batch* batch);
  * backward as synth_forward and synth_backward define them, Secs. 2.1, 6)
  * (PZ_MODE_FWD or PZ_MODE_FWD_BWD): every stage runs as one
  * persistent launch whose workgroups take (star, item) work from a queue
- * spanning all stars.  Enqueue-only: no host synchronisation, allocation or
+ * spanning all stars; the transfer and reverse transfer of stars with
+ * continuum scattering (Eq. 6) run in launches of their own after the
+ * others'.  Enqueue-only: no host synchronisation, allocation or
  * memset, so the call may be captured in a hipGraph and replayed.  Results
  * are bitwise equal to per-star synth_forward / pz_chi2_seed /
  * synth_backward calls with the same plans. */

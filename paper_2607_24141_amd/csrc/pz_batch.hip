@@ -241,6 +241,7 @@ struct pz_batch {
     bool any_center;      // some star uses the centre test
     int max_d;            // largest depth count of the stars
     int min_d;            // smallest depth count of the stars
+    std::vector<StarDev> sc_stars;   // stars with continuum scattering (their own flux and reverse launches)
     std::vector<const pz_plan*> plans;
     int n_items[N_PHASE];
     int2* items[N_PHASE];
@@ -303,8 +304,9 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
         int rc = check_atmos(st.plan, &st.atm);
         if (rc) return rc;
         if ((rc = check_params(&st.par))) return rc;
-        if (st.atm.sigma_c)
-            return set_error(PZ_E_UNSUPPORTED, "the batched launch has no scattering transfer (use synth_forward)");
+        if (st.atm.sigma_c && !st.plan->scatter_ws)
+            return set_error(PZ_E_INVALID_ARG,
+                             "a star has sigma_c but its plan was built without PZ_FLAG_SCATTERING");
         if (!st.F || !st.Fc) return set_error(PZ_E_INVALID_ARG, "every star needs F and Fc");
         if (st.y && !(st.sigma > 0.0f)) return set_error(PZ_E_INVALID_ARG, "sigma must be > 0 with a target y");
         const pz_plan* p = st.plan;
@@ -329,11 +331,13 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
         for (long k = 0; k < (nld + PARAM_ITEM - 1) / PARAM_ITEM; ++k) items[PH_PARAMS].push_back({b, (int)k});
         const int ph_op = s.tile_px == 32 ? PH_OP32 : (s.tile_px == 64 ? PH_OP64 : PH_OP128);
         for (int t = 0; t < s.n_tiles; ++t) items[ph_op].push_back({b, t});
+        // a star with scattering runs its transfer and reverse transfer in launches of its own
         for (int k = 0; k < (s.N + 511) / 512; ++k) {
-            items[PH_FLUX].push_back({b, k});
+            if (!s.scatter) items[PH_FLUX].push_back({b, k});
             if (st.y) items[PH_SEED].push_back({b, k});
         }
-        for (int k = 0; k < (s.N + 63) / 64; ++k) items[PH_REVERSE].push_back({b, k});
+        if (!s.scatter)
+            for (int k = 0; k < (s.N + 63) / 64; ++k) items[PH_REVERSE].push_back({b, k});
         if (st.y && st.loss) items[PH_LOSS].push_back({b, 0});
         for (int k = 0; k < (s.L + GATHER_ITEM - 1) / GATHER_ITEM; ++k) items[PH_GATHER].push_back({b, k});
         for (int k = 0; k < (s.L + 511) / 512; ++k) items[PH_SCATTER].push_back({b, k});
@@ -410,6 +414,8 @@ int pz_batch_create(int32_t n_star, const pz_star* stars, pz_batch** out) {
     bt->grid_rev = std::max(1, n_cu * 16);
     bt->plans.reserve(n_star);
     for (int b = 0; b < n_star; ++b) bt->plans.push_back(stars[b].plan);
+    for (int b = 0; b < n_star; ++b)
+        if (sd[b].scatter) bt->sc_stars.push_back(sd[b]);
     *out = bt;
     return PZ_OK;
 }
@@ -436,14 +442,23 @@ int synth_batch(const pz_batch* bt, int32_t mode, pz_stream stream) {
         batch_opacity<true>(bt, st);
     else
         batch_opacity<false>(bt, st);
-    kb_flux<<<grid(bt->grid512, n[PH_FLUX]), 512, 0, st>>>(bt->stars, it[PH_FLUX], n[PH_FLUX]);
+    if (n[PH_FLUX]) kb_flux<<<grid(bt->grid512, n[PH_FLUX]), 512, 0, st>>>(bt->stars, it[PH_FLUX], n[PH_FLUX]);
+    for (const StarDev& s : bt->sc_stars) {
+        const hipError_t e = launch_flux(s, st);
+        if (e != hipSuccess) return set_error(PZ_E_HIP, hipGetErrorString(e));
+    }
     if (n[PH_SEED])
         kb_seed<<<grid(bt->grid512, n[PH_SEED]), 512, 0, st>>>(bt->stars, it[PH_SEED], n[PH_SEED], bt->inv_s2, bt->ys);
     if (n[PH_LOSS])
         kb_loss<<<grid(bt->grid1024, n[PH_LOSS]), 1024, 0, st>>>(bt->stars, it[PH_LOSS], n[PH_LOSS], bt->inv_s2,
                                                                  bt->ys, bt->losses);
     if (mode == PZ_MODE_FWD_BWD) {
-        kb_reverse<<<grid(bt->grid_rev, n[PH_REVERSE]), 64, 0, st>>>(bt->stars, it[PH_REVERSE], n[PH_REVERSE]);
+        if (n[PH_REVERSE])
+            kb_reverse<<<grid(bt->grid_rev, n[PH_REVERSE]), 64, 0, st>>>(bt->stars, it[PH_REVERSE], n[PH_REVERSE]);
+        for (const StarDev& s : bt->sc_stars) {
+            const hipError_t e = launch_reverse_scan(s, st);
+            if (e != hipSuccess) return set_error(PZ_E_HIP, hipGetErrorString(e));
+        }
         kb_gather<<<grid(bt->grid_gather, n[PH_GATHER]), 512, 0, st>>>(bt->stars, it[PH_GATHER], n[PH_GATHER],
                                                                         bt->ctr + 3);
         kb_scatter<<<grid(bt->grid512, n[PH_SCATTER]), 512, 0, st>>>(bt->stars, it[PH_SCATTER], n[PH_SCATTER]);
@@ -452,7 +467,10 @@ int synth_batch(const pz_batch* bt, int32_t mode, pz_stream stream) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(PZ_E_HIP, hipGetErrorString(e));
-    for (const pz_plan* p : bt->plans) const_cast<pz_plan*>(p)->ws_valid = false;
+    for (const pz_plan* p : bt->plans) {
+        const_cast<pz_plan*>(p)->ws_valid = false;
+        const_cast<pz_plan*>(p)->sc_ok = false;
+    }
     return PZ_OK;
 }
 

@@ -90,6 +90,46 @@ def test_batch_bitwise_equals_per_star(gpu_lib, mode):
     batch.destroy()
 
 
+def _scatter_stars(pz):
+    """Two stars with continuum scattering (Eq. 6; one with a target and its
+    chi^2 seed) beside a plain one."""
+    import copy
+    stars = []
+    for k, (L, N, D, sig) in enumerate([(30, 600, 72, 0.7), (25, 500, 72, 0.0), (40, 700, 40, 2.0)]):
+        wl = W.tiny(seed=91 + k, L=L, N=N, D=D, S=4, n_molecular=1)
+        wl.params = W.random_params(np.random.default_rng(91 + k), L, 4, 1.3)
+        if sig:
+            wl.atm = copy.deepcopy(wl.atm)
+            wl.atm.sigma_c = sig * (1.0 + 0.5 * np.sin(0.7 * np.arange(D)))
+            wl.atm.sigma_alpha = 0.0
+        stars.append(Star(pz, wl, 32, target=(k == 0), seed=k))
+    return stars
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_with_scattering_stars_bitwise(gpu_lib, mode):
+    """Stars with continuum scattering in a batch: their transfer and reverse
+    transfer run in launches of their own, bitwise equal to per-star calls."""
+    pz = gpu_lib
+    stars = _scatter_stars(pz)
+    batch = pz.Batch([s.descr(pz) for s in stars])
+    print("synth_batch with scattering stars, mode", mode, flush=True)
+    pz.synth_batch(batch, mode)
+    torch.cuda.synchronize()
+    got = [s.outputs() for s in stars]
+    for s in stars:
+        s.sequential(pz, mode)
+    torch.cuda.synchronize()
+    for k, s in enumerate(stars):
+        ref = s.outputs()
+        n = 2 if mode == 1 else len(ref)
+        for a, b in zip(got[k][:n], ref[:n]):
+            np.testing.assert_array_equal(a, b)
+        if s.y is not None:
+            np.testing.assert_array_equal(got[k][-1], ref[-1])
+    batch.destroy()
+
+
 @pytest.mark.parametrize("chunk", [1, 3, 5])
 def test_batch_small_lds_chunks_bitwise(gpu_lib, chunk):
     """The batch kernels' chunk loop (one body, the LDS buffer chosen at run
@@ -118,11 +158,12 @@ def test_batch_small_lds_chunks_bitwise(gpu_lib, chunk):
     batch.destroy()
 
 
-def test_batch_graph_replay(gpu_lib):
+@pytest.mark.parametrize("which", ["plain", "scattering"])
+def test_batch_graph_replay(gpu_lib, which):
     """The whole forward+backward batch captured in one graph; every replay
     (with eager work and synchronisations in between) equals the eager run."""
     pz = gpu_lib
-    stars = _stars(pz)
+    stars = _stars(pz) if which == "plain" else _scatter_stars(pz)
     batch = pz.Batch([s.descr(pz) for s in stars])
     pz.synth_batch(batch, pz.PZ_MODE_FWD_BWD)
     torch.cuda.synchronize()
