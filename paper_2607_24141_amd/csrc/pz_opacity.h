@@ -117,7 +117,7 @@ __device__ __forceinline__ void stage_rows(const StarDev& s, int l0, int c, int 
     const int D = scalar_opaque(s.D), stride = scalar_opaque((nch - 1) * s.D);
     const int n = nc * D;
     const int lane = threadIdx.x % WAVE;
-    const float inv_d = 1.0f / (float)D;
+    const float inv_d = __builtin_amdgcn_rcpf((float)D);   // to 1 ulp: ample for the split below
     const char* lp = scalar_base(s.lp + row0);
     const char* zm = CT ? scalar_base(s.zmax + row0) : nullptr;
 #pragma unroll
@@ -278,7 +278,9 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
 
     const int nl = l1 - l0;
     const int nch = (nl + chunk - 1) / chunk;
-    auto lines_in = [&](int c) { return (nl - c + nch - 1) / nch; };
+    // chunk c holds lines c, c + nch, ...: nl / nch of them, one more for c < nl % nch
+    const int per_chunk = nch ? nl / nch : 0, extra = nch ? nl - per_chunk * nch : 0;
+    auto lines_in = [&](int c) { return per_chunk + (c < extra ? 1 : 0); };
     constexpr bool DB = Lds::NB == 2;                  // double-buffered chunks
     static_assert(!CT || !DB, "the centre test stages one buffer");
     XFields<WPX> f;
