@@ -289,7 +289,7 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
     // into fcur, and after the sum chunk c + 1's detunings go to nxs from
     // fnext (its fields, copied during chunk c - 1); else chunk c + 1's
     // fields are loaded into registers first and its detunings written after.
-    auto chunk_pass = [&](int c, const float4* rows, const float* xs, float4* nrows, float* nxs, int* fcur,
+    auto chunk_pass = [&](int c, const float4* __restrict__ rows, const float* __restrict__ xs, float4* __restrict__ nrows, float* __restrict__ nxs, int* fcur,
                           const int* fnext) __attribute__((always_inline)) {
         const int nc = lines_in(c);
         const bool more = DB && c + 1 < nch;
@@ -377,8 +377,9 @@ __device__ __forceinline__ void opacity_tile_body(const StarDev& s, int tile, in
                 if (c + 1 < nch) chunk_pass(c + 1, sm.lp1, sm.x1, sm.lp0, sm.x0, sm.f1, sm.f0);
             }
         } else {
-            // One loop body, the buffer chosen at run time (fewer registers;
-            // the loads of a chunk then wait for the copies in flight).
+            // One loop body, the buffer chosen at run time (fewer registers).
+            // The restrict-qualified buffers of chunk_pass tell the compiler
+            // that the copies in flight never land in the rows being read.
             for (int c = 0; c < nch; ++c) {
                 const bool odd = c & 1;
                 chunk_pass(c, odd ? sm.lp1 : sm.lp0, odd ? sm.x1 : sm.x0, odd ? sm.lp0 : sm.lp1,

@@ -766,8 +766,9 @@ __device__ __forceinline__ float wave_sum(float x) {
 // node-pair sums: 1e-6, 1e-6, 1.6e-4), in 34 operations against 43.
 static constexpr float kFarZ2 = 64.0f, kFarB = 4.0f;
 
-__device__ __forceinline__ void far_series_KHD(float b, float z2, float Ka, float& KH, float& KaHa, float& KX) {
-    const float r = __builtin_amdgcn_rcpf(z2);
+// The series' sums: H = c r ph, a dH/da = c r pa, X = c r^2 px, c = a/sqrt(pi).
+__device__ __forceinline__ void far_series(float b, float z2, float& r, float& ph, float& pa, float& px) {
+    r = __builtin_amdgcn_rcpf(z2);
     const float e2 = fmaf(-2.0f, b, 3.75f), e3 = fmaf(-15.0f, b, 13.125f);
     const float e4 = fmaf(fmaf(12.0f, b, -105.0f), b, 59.0625f);
     const float f1 = fmaf(-2.0f, b, 1.5f), f2 = fmaf(-12.0f, b, 3.75f);
@@ -775,13 +776,9 @@ __device__ __forceinline__ void far_series_KHD(float b, float z2, float Ka, floa
     const float f4 = fmaf(fmaf(180.0f, b, -420.0f), b, 59.0625f);
     const float g2 = fmaf(4.0f, b, -15.0f), g3 = fmaf(60.0f, b, -78.75f);
     const float g4 = fmaf(fmaf(-48.0f, b, 630.0f), b, -472.5f);
-    const float ph = fmaf(fmaf(fmaf(fmaf(e4, r, e3), r, e2), r, 1.5f), r, 1.0f);
-    const float pa = fmaf(fmaf(fmaf(fmaf(f4, r, f3), r, f2), r, f1), r, 1.0f);
-    const float px = fmaf(fmaf(fmaf(g4, r, g3), r, g2), r, -3.0f);
-    const float kr = Ka * kInvSqrtPiF * r;
-    KH = kr * ph;
-    KaHa = kr * pa;
-    KX = kr * r * px;
+    ph = fmaf(fmaf(fmaf(fmaf(e4, r, e3), r, e2), r, 1.5f), r, 1.0f);
+    pa = fmaf(fmaf(fmaf(fmaf(f4, r, f3), r, f2), r, f1), r, 1.0f);
+    px = fmaf(fmaf(fmaf(g4, r, g3), r, g2), r, -3.0f);
 }
 
 // One call per wavefront; l must be wavefront-uniform; pw holds the H and L
@@ -827,21 +824,28 @@ __device__ __forceinline__ void gather_body(const StarDev& s, int l, int lane, c
                     if (CT && !(fmaf(v, v, q.y) <= zm[j])) continue;
                     const float gj = g[(size_t)j * s.Npad];
                     const float u = v * v, z2 = u + q.y;
-                    float KH, KaHa, KX;
-                    if (__all(z2 >= kFarZ2 && q.y <= kFarB))
-                        far_series_KHD(q.y, z2, q.w, KH, KaHa, KX);
-                    else
-                        voigt_KHD(q.y, q.z, q.w, v, u, pw, KH, KaHa, KX);
                     const float4 e = lp[MAXD + j];
-                    sgf = fmaf(gj, KH, sgf);
-                    sxi = fmaf(gj * KX, e.x, sxi);
+                    // g K H = w th, g K a dH/da = w ta, g K X e.x = w tx
+                    float w, th, ta, tx;
+                    if (wave_all(z2 >= kFarZ2) && wave_all(q.y <= kFarB)) {
+                        float r;
+                        far_series(q.y, z2, r, th, ta, tx);
+                        w = (gj * r) * (q.w * kInvSqrtPiF);
+                        tx *= r * e.x;
+                    } else {
+                        voigt_KHD(q.y, q.z, q.w, v, u, pw, th, ta, tx);
+                        w = gj;
+                        tx *= e.x;
+                    }
+                    sgf = fmaf(w, th, sgf);
+                    sxi = fmaf(w, tx, sxi);
                     if (FAM) {
-                        const float t = gj * KaHa;
+                        const float t = w * ta;
                         sd = fmaf(t, e.y, sd);
                         sds = fmaf(t, e.z, sds);
                         sdw = fmaf(t, e.w, sdw);
                     } else {
-                        sd = fmaf(gj, KaHa, sd);
+                        sd = fmaf(w, ta, sd);
                     }
                 }
             }

@@ -192,6 +192,13 @@ __device__ __forceinline__ void core_w(double a, double v, double& wr, double& w
 }
 
 // ------------------------------------------------------------- dispatch
+// Wavefront votes on the lane mask of a compare (HIP's __all and __any first
+// turn the predicate into a per-lane 0/1 value and compare that again).
+__device__ __forceinline__ bool wave_all(bool c) {
+    return __builtin_amdgcn_ballot_w64(c) == __builtin_amdgcn_read_exec();
+}
+__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
+
 // Line-depth parameters arrive as (a^2, K, K a) with K the line-strength
 // factor; the functions return K-scaled results.  Every branch on __any /
 // __all is wavefront-uniform; the tests run in order of how often each tier
@@ -245,17 +252,17 @@ __device__ __forceinline__ void voigt_KHD(float a2, float K, float Ka, float v, 
                                           float& KaHa, float& KX) {
     const float z2 = u + a2;
     float h, ha, x;
-    if (__all(z2 >= PZ_VOIGT_TIER2_R2)) {
-        if (__any(z2 < PZ_VOIGT_TIER3_R2))
+    if (wave_all(z2 >= PZ_VOIGT_TIER2_R2)) {
+        if (wave_any(z2 < PZ_VOIGT_TIER3_R2))
             wing_SD<2>(a2, z2, PZ_GH4_T2, PZ_GH4_W, h, ha, x);
         else
             wing_SD<1>(a2, z2, PZ_GH2_T2, PZ_GH2_W, h, ha, x);
-    } else if (!__any(z2 < PZ_VOIGT_WING_R2) || z2 >= PZ_VOIGT_WING_R2) {
+    } else if (!wave_any(z2 < PZ_VOIGT_WING_R2) || z2 >= PZ_VOIGT_WING_R2) {
         wing_SD<3>(a2, z2, PZ_GH6_T2, PZ_GH6_W, h, ha, x);
     } else {
         if (a2 <= PZ_VOIGT_A2_SMALL) {
             float KaL;
-            if (__any(a2 > PZ_VOIGT_A2_TINY))
+            if (wave_any(a2 > PZ_VOIGT_A2_TINY))
                 coreP_KHL<true>(a2, K, Ka, v, pw, KH, KaL);
             else
                 coreP_KHL<false>(a2, K, Ka, v, pw, KH, KaL);
