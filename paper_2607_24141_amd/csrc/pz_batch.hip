@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64) void kb_reverse(const StarDev* __restrict__ sta
 
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void kb_gather(const StarDev* __restrict__ stars, const int2* __restrict__ items, int n, int* ctr) {
     __shared__ int s_it;
-    __shared__ float4 pw[PZ_PW_N * 8];
+    __shared__ float4 pw[2 * PZ_PW_LDS];
     __shared__ float4 lq[512 / WAVE][2 * MAXD];
     load_pw_table(pw, true);                           // visible after the first item fetch's barrier
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;

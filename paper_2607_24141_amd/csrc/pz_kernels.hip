@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64) void k_reverse_scan_e2(StarDev s) {
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_gather(StarDev s) {
-    __shared__ float4 pw[PZ_PW_N * 8];
+    __shared__ float4 pw[2 * PZ_PW_LDS];
     __shared__ float4 lq[256 / WAVE][2 * MAXD];
     load_pw_table(pw, true);
     const int w = threadIdx.x / WAVE;

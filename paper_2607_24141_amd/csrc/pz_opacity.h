@@ -77,7 +77,7 @@ static constexpr int NFIELD = 5;
     __shared__ int sm##_f0[(CT) ? 1 : NFIELD * MAX_CHUNK];                                 \
     __shared__ int sm##_f1[(CT) ? 1 : NFIELD * MAX_CHUNK];                                 \
     __shared__ float sm##_zmax[(CT) ? MAX_CHUNK * MAXD : 1];                               \
-    __shared__ float4 sm##_pw[PZ_PW_N * 4];                                                \
+    __shared__ float4 sm##_pw[PZ_PW_LDS];                                                \
     const OpacityLds<WPX, CT> sm { sm##_lp0, sm##_lp1, sm##_x0, sm##_x1, sm##_f0, sm##_f1, sm##_zmax, sm##_pw }
 
 // A wavefront-uniform pointer the compiler treats as opaque, held in scalar

@@ -105,7 +105,15 @@ __device__ __forceinline__ float sinc_t(float t) {
 
 // Piecewise tables of the small-damping core (in LDS): interval k of |v|
 // holds [P0_0..P0_3 | P0_4 P0_5 P2_0 P2_1 | P2_2 P2_3 P2_4 c | P4_0 P4_1 P4_2 0],
-// four float4 per interval; the table for L follows the one for H.
+// four float4 at a stride of five (the fifth unused): a 16-byte read covers
+// four of the 32 banks, and at a stride of 20 words eight neighbouring
+// intervals start in eight different bank quarters, so lanes in different
+// intervals read without bank conflicts (at a stride of 16 words all even
+// intervals would share banks, and all odd ones).  The table for L follows
+// the one for H.
+static constexpr int PZ_PW_STRIDE = 5;
+static constexpr int PZ_PW_LDS = PZ_PW_N * PZ_PW_STRIDE;   // float4 per table in LDS
+
 struct PwPoint {
     int k;       // interval
     float t;     // |v| - centre
@@ -115,7 +123,7 @@ __device__ __forceinline__ PwPoint pw_point(float v, const float4* tab) {
     const float av = fabsf(v);
     PwPoint p;
     p.k = min((int)(av * PZ_PW_INV_H), PZ_PW_N - 1);
-    p.t = av - tab[4 * p.k + 2].w;
+    p.t = av - tab[PZ_PW_STRIDE * p.k + 2].w;
     return p;
 }
 
@@ -137,7 +145,7 @@ __device__ __forceinline__ float pw_poly(const float4* T, float t, float a2) {
 template <bool FULL>
 __device__ __forceinline__ float coreP_KH_acc(float acc, float a2, float K, float Ka, float v, const float4* pw) {
     const PwPoint p = pw_point(v, pw);
-    const float lam = pw_poly<FULL>(pw + 4 * p.k, p.t, a2);
+    const float lam = pw_poly<FULL>(pw + PZ_PW_STRIDE * p.k, p.t, a2);
     const float u = v * v;
     const float g = __expf(a2 - u);
     return fmaf(Ka, lam, fmaf(K * g, cos_t<FULL>((4.0f * a2) * u), acc));
@@ -149,8 +157,8 @@ template <bool FULL>
 __device__ __forceinline__ void coreP_KHL(float a2, float K, float Ka, float v, const float4* pw, float& KH,
                                           float& KaL) {
     const PwPoint p = pw_point(v, pw);
-    const float lam = pw_poly<FULL>(pw + 4 * p.k, p.t, a2);
-    const float mu = pw_poly<FULL>(pw + 4 * (PZ_PW_N + p.k), p.t, a2);
+    const float lam = pw_poly<FULL>(pw + PZ_PW_STRIDE * p.k, p.t, a2);
+    const float mu = pw_poly<FULL>(pw + PZ_PW_STRIDE * (PZ_PW_N + p.k), p.t, a2);
     const float u = v * v;
     const float t = (4.0f * a2) * u;
     const float Kg = K * __expf(a2 - u);
@@ -163,8 +171,9 @@ __device__ __forceinline__ void coreP_KHL(float a2, float K, float Ka, float v, 
 __device__ __forceinline__ void load_pw_table(float4* dst, bool with_L) {
     float* d = reinterpret_cast<float*>(dst);
     for (int k = threadIdx.x; k < PZ_PW_N * 16; k += blockDim.x) {
-        d[k] = PZ_PW_TAB[k];
-        if (with_L) d[PZ_PW_N * 16 + k] = PZ_PW_MU_TAB[k];
+        const int o = (k / 16) * (4 * PZ_PW_STRIDE) + k % 16;
+        d[o] = PZ_PW_TAB[k];
+        if (with_L) d[4 * PZ_PW_LDS + o] = PZ_PW_MU_TAB[k];
     }
 }
 
