@@ -111,6 +111,43 @@ def test_vjp_tiny_vs_oracle(gpu_lib, seed, L, N, D, xi, quad):
         assert abs(g[3][0]) <= 1e-5 * np.max(np.abs(ref["g_loggf"])) + 1e-30
 
 
+def test_vjp_far_wing_terms_vs_oracle(gpu_lib):
+    """A seed that vanishes wherever any line, at any depth, has v^2 + a^2 < 64
+    at the pixel: every term of the line gradients then comes from a far-wing
+    evaluation of H, a dH/da and X (the gather's asymptotic series where a
+    whole step qualifies, else the four- and two-node sums), so the gradients
+    are held far below the general 1e-3 rule.  The bounds are those
+    evaluations' worst cases over the far wing (H 1e-6, a dH/da 1.5e-5,
+    X 1.6e-4 relative) scaled down to this case, whose terms sit mostly well
+    beyond |z| = 8 and at small a, where the series is far more accurate
+    (measured 1e-7, 1e-7, 1.1e-6): a wrong coefficient of the series' leading
+    orders shows.  A positive seed keeps the terms of each gradient of one
+    sign."""
+    pz = gpu_lib
+    wl = W.tiny(seed=41, L=24, N=2400, D=72, S=4, xi=1.3)
+    rng = np.random.default_rng(41)
+    wl.params = W.random_params(rng, wl.lines.L, 4, 1.3)
+    N = wl.grid.N
+    p_idx, l_idx = O.window_pairs(wl.grid, wl.lines, wl.window_nm, np.arange(N))
+    prm = wl.params
+    lp = O.line_depth_params(wl.atm, wl.lines, prm.dgf, prm.ddamp, prm.dA, prm.xi_kms)
+    nu_i = O.C_LIGHT / (O.wavelengths_nm(wl.grid, np.arange(N)) * 1.0e-7)
+    v = (nu_i[p_idx][:, None] - lp["nu_l"][l_idx][:, None]) / lp["dnu"][l_idx]
+    z2 = (v * v + lp["a"][l_idx] ** 2).min(axis=1)
+    near = np.zeros(N, bool)
+    near[p_idx[z2 < 64.5]] = True
+    assert np.max(lp["a"]) ** 2 <= 4.0                        # the series' damping range
+    far = ~near & np.isin(np.arange(N), p_idx)
+    assert far.sum() > 0.3 * N, far.sum()
+    s = np.where(far, rng.uniform(0.5, 1.5, N), 0.0).astype(np.float32)
+    g = gpu_vjp(pz, wl, s)
+    ref = O.adjoint(wl, wl.params, s.astype(np.float64))
+    for got, r, tol, name in ((g[0], ref["g_loggf"], 1e-5, "loggf"), (g[1], ref["g_damp"], 2e-5, "damp"),
+                              (g[2], ref["g_abund"], 1e-5, "abund"), (g[3], [ref["g_xi"]], 5e-5, "xi")):
+        err = grad_close(got, r, rtol=tol, name=name)
+        print("far-wing terms: %s worst relative error %.2e" % (name, err))
+
+
 def test_vjp_abundance_is_species_sum(gpu_lib):
     """dL/d dA_s equals the sum of dL/d dgf over the lines of species s (fixed atmosphere)."""
     wl = W.tiny(seed=31, L=80, N=1200, D=72, S=5, n_molecular=1)
