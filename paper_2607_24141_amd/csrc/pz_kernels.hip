@@ -164,12 +164,22 @@ __global__ __launch_bounds__(64) void k_reverse_scan_e2(StarDev s) {
     dev_reverse_scan_e2(s, i, col + threadIdx.x);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod 8).
+// Renumbering them so that each XCD takes one contiguous range of blocks puts
+// neighbouring lines, whose windows read the same dL/dkappa columns, on the
+// same XCD and so in the same L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_contiguous_block(int b, int nb) {
+    const int x = b % 8, p = b / 8, q = nb / 8, r = nb % 8;
+    return x * q + min(x, r) + p;
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_gather(StarDev s) {
     __shared__ float4 pw[2 * PZ_PW_LDS];
     __shared__ float4 lq[256 / WAVE][2 * MAXD];
     load_pw_table(pw, true);
     const int w = threadIdx.x / WAVE;
-    const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / WAVE) + w);
+    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int l = __builtin_amdgcn_readfirstlane(blk * (256 / WAVE) + w);
     stage_line_params(s, l, threadIdx.x % WAVE, lq[w]);
     __syncthreads();
     dev_gather(s, l, threadIdx.x % WAVE, pw, lq[w]);
